@@ -1,0 +1,235 @@
+/*
+ * bfs.h -- C ABI of the MI355X (gfx950) breadth-first-search hot path.
+ *
+ * The problem (Section 2, Preliminaries): an undirected graph G = (V, E) with
+ * both (u,v) and (v,u) stored, and a root r. The output is d[v], the number of
+ * hops from r to v, or "infinity" when no path exists. This library computes
+ * d by the level-synchronous top-down traversal of Algorithm 1, organised as in
+ * Algorithm 2 of Section 3: a local expansion of the owned frontier into a
+ * global next-frontier bitmap (Phase 1) followed by a frontier-synchronisation
+ * merge of that bitmap with the bitmaps received from other compute nodes
+ * (Phase 2). With one compute node the merge has no incoming bitmaps.
+ *
+ * Conventions used by every entry point
+ *   - All graph, workspace, output and bitmap pointers are DEVICE pointers
+ *     (hipMalloc'd or torch CUDA tensors) unless marked "host".
+ *   - Distances are int32 with -1 meaning infinity (the uint8 batched form
+ *     uses 255). Parents are int32: parent[root] = root, -1 if unreached, and
+ *     otherwise the smallest-id neighbour one level closer to the root.
+ *   - Bitmaps are uint64 words: vertex v is bit (v & 63) of word (v >> 6);
+ *     bits at positions >= n_global in the last word must be zero.
+ *   - Every call returns a bfs_status. No C++ exception crosses the ABI; after
+ *     an error, bfs_last_error() describes it and the plan stays usable.
+ *   - The caller owns all device memory, including the workspace, which must
+ *     outlive the plan. After bfs_plan_create the library allocates no device
+ *     memory: every buffer has a fixed size independent of the level and the
+ *     source (the paper preallocates its exchange buffers, Section 3 "Fanout &
+ *     Trade-offs", and bounds memory use by the fanout).
+ *   - All device work is ordered on the plan's HIP stream.
+ */
+#ifndef BFS_MI355X_H
+#define BFS_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bfs_status;
+#define BFS_OK 0
+#define BFS_ERR_ARG 1        /* invalid argument (null pointer, bad source, bad sizes) */
+#define BFS_ERR_WORKSPACE 2  /* workspace smaller than bfs_workspace_size() */
+#define BFS_ERR_HIP 3        /* a HIP runtime call failed; message names it */
+#define BFS_ERR_DEPTH 4      /* a uint8 batched distance would exceed 254 */
+#define BFS_ERR_CAPACITY 5   /* a batched query can never fit the plan's lanes */
+#define BFS_ERR_EXCHANGE 6   /* the exchange callback returned nonzero */
+#define BFS_ERR_STATE 7      /* call out of order (e.g. merge before begin) */
+#define BFS_ERR_TIMEOUT 8    /* bfs_batch_wait timed out; the ticket stays valid */
+#define BFS_ERR_DEVICE 9     /* a device-side safety limit tripped (see message) */
+
+typedef struct bfs_plan_s *bfs_plan_t;
+
+/*
+ * One graph, or one compute node's 1D share of it (Section 4, "Graph
+ * Partitioning": consecutive vertex ranges per node). The node owns vertices
+ * [v_begin, v_end) and stores their adjacency: row_ptr has v_end - v_begin + 1
+ * entries with row_ptr[0] == 0 and row_ptr[last] == m; col holds m GLOBAL
+ * vertex ids. For a whole graph, v_begin = 0 and v_end = n_global. The whole
+ * graph must be symmetric (undirected), with n_global < 2^31.
+ */
+typedef struct {
+  int64_t n_global;
+  int64_t v_begin;
+  int64_t v_end;
+  int64_t m;
+  const int64_t *row_ptr; /* device */
+  const int32_t *col;     /* device */
+} bfs_graph;
+
+/*
+ * Exchange callback for partitioned runs, called by bfs_run once per level
+ * after the local expansion (Algorithm 2, between Phase 1 and Phase 2).
+ * local_next is the node's global queue for the level as a bitmap (device,
+ * read-only for the callback). The callback sets *incoming to a host array of
+ * *k device bitmap pointers: the messages received from the butterfly partners
+ * for this level. Return 0 on success; nonzero aborts the run with
+ * BFS_ERR_EXCHANGE. The stream is synchronised before the call.
+ */
+typedef int32_t (*bfs_exchange_fn)(void *ctx, int32_t level, const uint64_t *local_next,
+                                   const uint64_t *const **incoming, int32_t *k);
+
+#define BFS_LOOP_AUTO 0       /* device-resident loop when no exchange callback */
+#define BFS_LOOP_HOST 1       /* one launch per phase, host reads the new count */
+#define BFS_LOOP_PERSISTENT 2 /* whole traversal in one cooperative launch */
+
+typedef struct {
+  void *hip_stream;        /* hipStream_t; NULL = the null stream */
+  int32_t loop_mode;       /* BFS_LOOP_* */
+  int32_t small_bin;       /* degree bins b < small_bin -> lane-group tier; 0 = tuned default */
+  int32_t wave_bin;        /* bins small_bin <= b < wave_bin -> wave tier, else block tier */
+  int32_t chunk_edges;     /* edges per block-tier work item (power of two); 0 = default */
+  int32_t grid_blocks;     /* workgroups for device-resident loops; 0 = fill the chip */
+  int32_t batch_lanes;     /* 64-source lane words per graph for batched BFS; 0 = none */
+  int32_t collect_stats;   /* nonzero: per-level frontier sizes and degree-bin histograms */
+  bfs_exchange_fn exchange;
+  void *exchange_ctx;
+} bfs_options;
+
+/* Fills *o with defaults (all zero / NULL, loop_mode AUTO). */
+void bfs_options_default(bfs_options *o);
+
+typedef struct {
+  int32_t levels;        /* number of nonempty levels = max distance + 1 */
+  int64_t reached;       /* vertices with a finite distance (all n_global) */
+  int64_t edges_scanned; /* sum of degrees of the owned frontier vertices */
+  float ms;              /* device time of the traversal (HIP events) */
+} bfs_stats;
+
+#define BFS_MAX_LEVEL_STATS 4096
+#define BFS_NUM_BINS 34 /* degree bin b = 0 for degree 0, else 1 + floor(log2(degree)) */
+
+/*
+ * Bytes of device workspace bfs_plan_create needs for these graphs and
+ * options (the largest of the graphs for single-source runs, plus batched
+ * lane state per graph when batch_lanes > 0). Host pointers in, *bytes out.
+ */
+bfs_status bfs_workspace_size(const bfs_graph *graphs, int32_t ngraphs, const bfs_options *o,
+                              size_t *bytes);
+
+/*
+ * Creates a plan over ngraphs graphs (host array of descriptors; the device
+ * arrays they point to must outlive the plan). workspace: device memory of at
+ * least bfs_workspace_size() bytes, 256-byte aligned, owned by the caller.
+ * Autotuned tier thresholds are chosen here when the options leave them 0.
+ */
+bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_options *o,
+                           void *workspace, size_t ws_bytes, bfs_plan_t *out);
+
+/* Destroys the plan (host object only). Safe on NULL. */
+void bfs_plan_destroy(bfs_plan_t p);
+
+/* Last error message of the plan (or of the last failed create when p is NULL). */
+const char *bfs_last_error(bfs_plan_t p);
+
+/*
+ * Single-source traversal (Algorithm 1; Algorithm 2 when the graph is a
+ * share). Writes dist[0..n_global) (device, int32) and, if parent != NULL,
+ * canonical parents for the owned range (device, int32[n_global]; entries
+ * outside the owned range are -2 for reached vertices). source must be in
+ * [0, n_global); a source outside the owned range is legal (every node sets
+ * the root's distance, only the owner enqueues it: Algorithm 2 set-up).
+ * Returns after the traversal has finished; st may be NULL.
+ */
+bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, int32_t *parent,
+                   bfs_stats *st);
+
+/*
+ * Step-wise form of bfs_run for callers that drive the level loop and the
+ * exchange themselves.
+ *   bfs_begin: reset (all distances infinity, root at 0, frontier {root} if
+ *     owned) into dist (device int32[n_global], kept by the plan until the
+ *     next bfs_begin).
+ *   bfs_expand: Phase 1 for the current level: every owned frontier vertex
+ *     scans its adjacency and marks unvisited neighbours in the node's
+ *     next-frontier bitmap. *local_next receives that bitmap's device address
+ *     (ceil(n_global/64) words) so it can be sent to partners.
+ *   bfs_merge_frontier: Phase 2 (Algorithm 2, frontier synchronisation) over k
+ *     incoming bitmaps (host array of k device pointers, k >= 0): every vertex
+ *     set in the local bitmap or any incoming one and not yet visited is new;
+ *     new vertices get distance level+1, and owned new vertices form the next
+ *     frontier. keep_next != 0 keeps the union in the local bitmap (the node's
+ *     global queue, for multi-round exchanges within a level; call again with
+ *     the next round's messages) and does not advance the level; keep_next == 0
+ *     finishes the level. *global_new and *owned_new (host, may be NULL)
+ *     receive the counts for this call; reading them synchronises the stream.
+ *     The traversal is over when a finished level has global_new == 0
+ *     (every node sees the same count after a full exchange).
+ *   bfs_finish: writes parents (if parent != NULL) and fills *st.
+ */
+bfs_status bfs_begin(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist);
+bfs_status bfs_expand(bfs_plan_t p, const uint64_t **local_next);
+bfs_status bfs_merge_frontier(bfs_plan_t p, const uint64_t *const *incoming, int32_t k,
+                              int32_t keep_next, int64_t *global_new, int64_t *owned_new);
+bfs_status bfs_finish(bfs_plan_t p, int32_t *parent, bfs_stats *st);
+
+/*
+ * Per-level statistics of the last traversal (collect_stats must be set):
+ * frontier[L] = owned frontier size at level L, hist[L*BFS_NUM_BINS + b] =
+ * frontier vertices of degree bin b at level L. Host arrays of max_levels and
+ * max_levels*BFS_NUM_BINS entries; *levels receives the number of levels.
+ */
+bfs_status bfs_level_stats(bfs_plan_t p, int64_t *frontier, int64_t *hist, int32_t max_levels,
+                           int32_t *levels);
+
+/* ------------------------------------------------------------------------ */
+/* Batched multi-source traversal and serving                               */
+/* ------------------------------------------------------------------------ */
+
+#define BFS_OUT_U8 0  /* uint8 distances, 255 = unreached, depth > 254 -> BFS_ERR_DEPTH */
+#define BFS_OUT_I32 1 /* int32 distances, -1 = unreached */
+
+typedef struct {
+  int32_t graph;   /* index into the plan's graphs (whole graphs only) */
+  int32_t out_type;/* BFS_OUT_U8 or BFS_OUT_I32 */
+  int64_t source;  /* in [0, n of that graph) */
+  void *out;       /* device, n entries of out_type */
+} bfs_query;
+
+#define BFS_BATCH_ONE_LAUNCH 1 /* run the whole batch together, return when queued */
+#define BFS_BATCH_STREAMING 2  /* hand queries to the serving scheduler as they arrive */
+
+typedef struct {
+  int32_t status;        /* BFS_OK or the first error of the batch */
+  int32_t nq;            /* queries in the ticket */
+  int64_t submit_ns;     /* host steady-clock times (ns) */
+  int64_t complete_ns;
+} bfs_batch_result;
+
+/*
+ * Submits nq queries (host array). With BFS_BATCH_ONE_LAUNCH the batch runs
+ * as one multi-source bitset traversal per graph (64 sources per uint64 lane
+ * word) and *ticket identifies it. With BFS_BATCH_STREAMING the queries join
+ * the plan's serving loop: they are admitted into free lanes when lane memory
+ * frees up and finish independently; *ticket identifies the group.
+ * Requires batch_lanes > 0 at plan creation.
+ */
+bfs_status bfs_batch_submit(bfs_plan_t p, const bfs_query *q, int32_t nq, uint32_t flags,
+                            uint64_t *ticket);
+
+/*
+ * Waits for a ticket (timeout_us < 0 waits forever). On BFS_OK, every output
+ * of the ticket is complete and *r (host, may be NULL) describes it.
+ */
+bfs_status bfs_batch_wait(bfs_plan_t p, uint64_t ticket, int64_t timeout_us,
+                          bfs_batch_result *r);
+
+/* Per-query completion times (host steady-clock ns) of a finished streaming
+ * ticket, in submission order. */
+bfs_status bfs_batch_times(bfs_plan_t p, uint64_t ticket, int64_t *complete_ns, int32_t nq);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BFS_MI355X_H */

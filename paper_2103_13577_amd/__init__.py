@@ -1,0 +1,296 @@
+"""Python binding of the MI355X BFS hot path (``libbfs.so``).
+
+Argument marshalling only: every step of the traversal runs in the HIP
+kernels behind the C ABI declared in ``include/bfs.h``. PyTorch supplies the
+device memory (graphs, workspace, outputs) and the stream. If the compiled
+library is missing the import of :func:`lib` raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbfs.so")
+
+BFS_OK = 0
+STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_WORKSPACE", 3: "ERR_HIP", 4: "ERR_DEPTH",
+                5: "ERR_CAPACITY", 6: "ERR_EXCHANGE", 7: "ERR_STATE", 8: "ERR_TIMEOUT",
+                9: "ERR_DEVICE"}
+LOOP_AUTO, LOOP_HOST, LOOP_PERSISTENT = 0, 1, 2
+OUT_U8, OUT_I32 = 0, 1
+BATCH_ONE_LAUNCH, BATCH_STREAMING = 1, 2
+NUM_BINS = 34
+MAX_LEVEL_STATS = 4096
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+EXCHANGE_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                               ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int32))
+
+
+class bfs_graph(ctypes.Structure):
+    _fields_ = [("n_global", ctypes.c_int64), ("v_begin", ctypes.c_int64),
+                ("v_end", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class bfs_options(ctypes.Structure):
+    _fields_ = [("hip_stream", ctypes.c_void_p), ("loop_mode", ctypes.c_int32),
+                ("small_bin", ctypes.c_int32), ("wave_bin", ctypes.c_int32),
+                ("chunk_edges", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("batch_lanes", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
+                ("exchange", EXCHANGE_FN), ("exchange_ctx", ctypes.c_void_p)]
+
+
+class bfs_stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("reached", ctypes.c_int64),
+                ("edges_scanned", ctypes.c_int64), ("ms", ctypes.c_float)]
+
+
+class bfs_query(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("out_type", ctypes.c_int32),
+                ("source", ctypes.c_int64), ("out", ctypes.c_void_p)]
+
+
+class bfs_batch_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("nq", ctypes.c_int32),
+                ("submit_ns", ctypes.c_int64), ("complete_ns", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libbfs.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it first (python __graft_entry__.py build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                              ctypes.c_uint64)
+    sig = {
+        "bfs_options_default": (None, [ctypes.POINTER(bfs_options)]),
+        "bfs_workspace_size": (i32, [ctypes.POINTER(bfs_graph), i32, ctypes.POINTER(bfs_options),
+                                     ctypes.POINTER(ctypes.c_size_t)]),
+        "bfs_plan_create": (i32, [ctypes.POINTER(bfs_graph), i32, ctypes.POINTER(bfs_options), vp,
+                                  ctypes.c_size_t, ctypes.POINTER(vp)]),
+        "bfs_plan_destroy": (None, [vp]),
+        "bfs_last_error": (ctypes.c_char_p, [vp]),
+        "bfs_run": (i32, [vp, i32, i64, vp, vp, ctypes.POINTER(bfs_stats)]),
+        "bfs_begin": (i32, [vp, i32, i64, vp]),
+        "bfs_expand": (i32, [vp, ctypes.POINTER(vp)]),
+        "bfs_merge_frontier": (i32, [vp, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(i64),
+                                     ctypes.POINTER(i64)]),
+        "bfs_finish": (i32, [vp, vp, ctypes.POINTER(bfs_stats)]),
+        "bfs_level_stats": (i32, [vp, vp, vp, i32, ctypes.POINTER(i32)]),
+        "bfs_batch_submit": (i32, [vp, ctypes.POINTER(bfs_query), i32, u32, ctypes.POINTER(u64)]),
+        "bfs_batch_wait": (i32, [vp, u64, i64, ctypes.POINTER(bfs_batch_result)]),
+        "bfs_batch_times": (i32, [vp, u64, vp, i32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+EXPORTED = ("bfs_options_default", "bfs_workspace_size", "bfs_plan_create", "bfs_plan_destroy",
+            "bfs_last_error", "bfs_run", "bfs_begin", "bfs_expand", "bfs_merge_frontier",
+            "bfs_finish", "bfs_level_stats", "bfs_batch_submit", "bfs_batch_wait",
+            "bfs_batch_times")
+
+
+class BfsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class DeviceGraph:
+    """A graph (or one node's 1D share of it) resident in device memory."""
+    n_global: int
+    v_begin: int
+    v_end: int
+    row_ptr: object  # torch int64 cuda tensor, v_end - v_begin + 1 entries
+    col: object      # torch int32 cuda tensor, m entries (global ids)
+
+    @property
+    def m(self) -> int:
+        return int(self.col.numel())
+
+    @classmethod
+    def from_csr(cls, csr, device="cuda", v_begin: int = 0, v_end: int | None = None):
+        torch = _torch()
+        v_end = csr.n if v_end is None else v_end
+        lo, hi = int(csr.row_ptr[v_begin]), int(csr.row_ptr[v_end])
+        rp = np.ascontiguousarray(csr.row_ptr[v_begin:v_end + 1] - lo, dtype=np.int64)
+        col = np.ascontiguousarray(csr.col[lo:hi], dtype=np.int32)
+        return cls(csr.n, v_begin, v_end, torch.from_numpy(rp).to(device),
+                   torch.from_numpy(col).to(device))
+
+    def c_struct(self) -> bfs_graph:
+        return bfs_graph(self.n_global, self.v_begin, self.v_end, self.m,
+                         self.row_ptr.data_ptr(), self.col.data_ptr() if self.m else 0)
+
+
+@dataclass
+class Stats:
+    levels: int
+    reached: int
+    edges_scanned: int
+    ms: float
+
+
+class Plan:
+    """A plan over one or more device graphs (C ABI ``bfs_plan_create``).
+
+    Owns its workspace (a torch uint8 tensor) and keeps the graphs alive.
+    """
+
+    def __init__(self, graphs, *, loop_mode=LOOP_AUTO, small_bin=0, wave_bin=0, chunk_edges=0,
+                 grid_blocks=0, batch_lanes=0, collect_stats=False, exchange=None, stream=None):
+        torch = _torch()
+        L = lib()
+        if isinstance(graphs, DeviceGraph):
+            graphs = [graphs]
+        self.graphs = list(graphs)
+        self._garr = (bfs_graph * len(self.graphs))(*[g.c_struct() for g in self.graphs])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        o = bfs_options()
+        L.bfs_options_default(ctypes.byref(o))
+        o.hip_stream = self.stream.cuda_stream
+        o.loop_mode = loop_mode
+        o.small_bin, o.wave_bin, o.chunk_edges = small_bin, wave_bin, chunk_edges
+        o.grid_blocks, o.batch_lanes, o.collect_stats = grid_blocks, batch_lanes, int(collect_stats)
+        self._exchange_py = exchange
+        self._exchange_keep = None
+        if exchange is not None:
+            self._cb = EXCHANGE_FN(self._exchange_trampoline)
+            o.exchange = self._cb
+        self.opts = o
+        nbytes = ctypes.c_size_t(0)
+        self._check(L.bfs_workspace_size(self._garr, len(self.graphs), ctypes.byref(o),
+                                         ctypes.byref(nbytes)), None)
+        self.workspace_bytes = int(nbytes.value)
+        self.workspace = torch.empty(max(self.workspace_bytes, 256) + 256, dtype=torch.uint8,
+                                     device=self.graphs[0].row_ptr.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        h = ctypes.c_void_p(0)
+        st = L.bfs_plan_create(self._garr, len(self.graphs), ctypes.byref(o), aligned,
+                               self.workspace_bytes + 256 - (aligned - base), ctypes.byref(h))
+        if st != BFS_OK:
+            raise BfsError(st, L.bfs_last_error(None).decode())
+        self.h = h
+
+    # -- plumbing -----------------------------------------------------------
+    def _check(self, st, h="self"):
+        if st != BFS_OK:
+            handle = self.h if h == "self" else None
+            msg = lib().bfs_last_error(handle)
+            raise BfsError(st, msg.decode() if msg else "")
+
+    def _exchange_trampoline(self, ctx, level, local_next, out_ptrs, out_k):
+        try:
+            ptrs = self._exchange_py(int(level), int(local_next or 0))
+        except Exception:  # an exception must not cross the C ABI
+            return 1
+        arr = (ctypes.c_void_p * max(len(ptrs), 1))(*[int(p) for p in ptrs])
+        self._exchange_keep = arr
+        out_ptrs[0] = ctypes.cast(arr, ctypes.c_void_p)
+        out_k[0] = len(ptrs)
+        return 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().bfs_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- single source -------------------------------------------------------
+    def run(self, graph: int, source: int, dist=None, parent: bool = False):
+        """Single-source traversal. Returns (dist, parent or None, Stats)."""
+        torch = _torch()
+        g = self.graphs[graph]
+        dev = g.row_ptr.device
+        if dist is None:
+            dist = torch.empty(g.n_global, dtype=torch.int32, device=dev)
+        par = torch.empty(g.n_global, dtype=torch.int32, device=dev) if parent else None
+        st = bfs_stats()
+        self._check(lib().bfs_run(self.h, graph, int(source), dist.data_ptr(),
+                                  par.data_ptr() if par is not None else None, ctypes.byref(st)))
+        return dist, par, Stats(st.levels, st.reached, st.edges_scanned, st.ms)
+
+    def begin(self, graph: int, source: int, dist):
+        self._check(lib().bfs_begin(self.h, graph, int(source), dist.data_ptr()))
+
+    def expand(self) -> int:
+        """Phase 1 of the current level; returns the device address of the
+        node's next-frontier bitmap."""
+        p = ctypes.c_void_p(0)
+        self._check(lib().bfs_expand(self.h, ctypes.byref(p)))
+        return int(p.value or 0)
+
+    def merge_frontier(self, incoming=(), keep_next: bool = False):
+        """Phase 2 over device bitmaps (torch uint64/int64 tensors or raw
+        addresses). Returns (global_new, owned_new) for the level so far."""
+        ptrs = [x if isinstance(x, int) else x.data_ptr() for x in incoming]
+        arr = (ctypes.c_void_p * max(len(ptrs), 1))(*ptrs)
+        gn, on = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._check(lib().bfs_merge_frontier(self.h, arr, len(ptrs), int(keep_next),
+                                             ctypes.byref(gn), ctypes.byref(on)))
+        return int(gn.value), int(on.value)
+
+    def finish(self, parent=None) -> Stats:
+        st = bfs_stats()
+        self._check(lib().bfs_finish(self.h, parent.data_ptr() if parent is not None else None,
+                                     ctypes.byref(st)))
+        return Stats(st.levels, st.reached, st.edges_scanned, st.ms)
+
+    def level_stats(self):
+        """(frontier sizes per level, degree-bin histogram [levels, 34])."""
+        f = np.zeros(MAX_LEVEL_STATS, dtype=np.int64)
+        h = np.zeros((MAX_LEVEL_STATS, NUM_BINS), dtype=np.int64)
+        nl = ctypes.c_int32(0)
+        self._check(lib().bfs_level_stats(self.h, f.ctypes.data, h.ctypes.data, MAX_LEVEL_STATS,
+                                          ctypes.byref(nl)))
+        return f[:nl.value].copy(), h[:nl.value].copy()
+
+    # -- batched / serving -----------------------------------------------------
+    def batch_submit(self, queries, flags=BATCH_ONE_LAUNCH) -> int:
+        """queries: list of (graph, source, out_tensor). Returns a ticket."""
+        torch = _torch()
+        arr = (bfs_query * max(len(queries), 1))()
+        for i, (gi, s, out) in enumerate(queries):
+            ot = OUT_U8 if out.dtype == torch.uint8 else OUT_I32
+            arr[i] = bfs_query(int(gi), ot, int(s), out.data_ptr())
+        t = ctypes.c_uint64(0)
+        self._check(lib().bfs_batch_submit(self.h, arr, len(queries), flags, ctypes.byref(t)))
+        return int(t.value)
+
+    def batch_wait(self, ticket: int, timeout_us: int = -1) -> bfs_batch_result:
+        r = bfs_batch_result()
+        self._check(lib().bfs_batch_wait(self.h, ticket, timeout_us, ctypes.byref(r)))
+        return r
+
+    def batch_times(self, ticket: int, nq: int) -> np.ndarray:
+        out = np.zeros(nq, dtype=np.int64)
+        self._check(lib().bfs_batch_times(self.h, ticket, out.ctypes.data, nq))
+        return out

@@ -1,0 +1,392 @@
+// C ABI of the single-source traversal: plans, workspace layout, the level
+// loop (device-resident or host-driven with an exchange callback), the
+// step-wise Phase 1 / Phase 2 calls and statistics. Declarations and their
+// contracts are in include/bfs.h.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bfs.h"
+#include "bfs_core.hpp"
+#include "plan.hpp"
+
+using namespace bfsk;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+bfs_status bfs_plan_s::fail(bfs_status st, const std::string &msg) {
+  err = msg;
+  return st;
+}
+
+bfs_status bfs_plan_s::hip_fail(hipError_t e, const char *what) {
+  err = std::string(what) + ": " + hipGetErrorString(e);
+  return BFS_ERR_HIP;
+}
+
+namespace bfsk {
+
+// Workspace regions for single-source runs, sized by the largest graph.
+void layout_single(const bfs_graph *g, int32_t ng, WsLayout &L, size_t &off) {
+  int64_t nmax = 0, omax = 1;
+  for (int i = 0; i < ng; ++i) {
+    nmax = std::max(nmax, g[i].n_global);
+    omax = std::max(omax, g[i].v_end - g[i].v_begin);
+  }
+  const int64_t words = (nmax + 63) / 64;
+  L.ctl = off; off = align_up(off + sizeof(Ctl), 256);
+  L.lvl_frontier = off; off = align_up(off + sizeof(int64_t) * kMaxStatLevels, 256);
+  L.lvl_hist = off; off = align_up(off + sizeof(uint32_t) * kMaxStatLevels * kNumBins, 256);
+  L.visited = off; off = align_up(off + sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), 256);
+  L.next = off; off = align_up(off + sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), 256);
+  for (int t = 0; t < 3; ++t)
+    for (int p = 0; p < 2; ++p) { L.q[t][p] = off; off = align_up(off + sizeof(int32_t) * (size_t)omax, 256); }
+  for (int p = 0; p < 2; ++p) { L.cstart[p] = off; off = align_up(off + sizeof(uint32_t) * (size_t)omax, 256); }
+}
+
+}  // namespace bfsk
+
+View bfs_plan_s::view(int32_t gi, int32_t *dist) const {
+  View v{};
+  const bfs_graph &g = graphs[gi];
+  char *b = (char *)ws;
+  v.n = g.n_global;
+  v.vb = g.v_begin;
+  v.ve = g.v_end;
+  v.m = g.m;
+  v.words = (g.n_global + 63) / 64;
+  v.rp = g.row_ptr;
+  v.col = g.col;
+  v.dist = dist;
+  v.visited = (uint64_t *)(b + lay.visited);
+  v.next = (uint64_t *)(b + lay.next);
+  for (int p = 0; p < 2; ++p) {
+    v.q0[p] = (int32_t *)(b + lay.q[0][p]);
+    v.q1[p] = (int32_t *)(b + lay.q[1][p]);
+    v.q2[p] = (int32_t *)(b + lay.q[2][p]);
+    v.cstart[p] = (uint32_t *)(b + lay.cstart[p]);
+  }
+  v.ctl = (Ctl *)(b + lay.ctl);
+  v.lvl_frontier = (int64_t *)(b + lay.lvl_frontier);
+  v.lvl_hist = (uint32_t *)(b + lay.lvl_hist);
+  v.small_bin = tune[gi].small_bin;
+  v.wave_bin = tune[gi].wave_bin;
+  v.chunk_shift = tune[gi].chunk_shift;
+  v.stats = opt.collect_stats ? 1 : 0;
+  return v;
+}
+
+int bfs_plan_s::wide_grid() const { return num_cus * 8; }
+
+int bfs_plan_s::merge_grid(int64_t words) const {
+  int64_t g = (words + kBlock - 1) / kBlock;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, (int64_t)num_cus * 8));
+}
+
+bfs_status bfs_plan_s::read_ctl(Ctl &c) {
+  hipError_t e = hipMemcpyAsync(&c, (char *)ws + lay.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(ctl)");
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return BFS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+void bfs_options_default(bfs_options *o) {
+  if (o) memset(o, 0, sizeof(*o));
+}
+
+bfs_status bfs_workspace_size(const bfs_graph *graphs, int32_t ngraphs, const bfs_options *o,
+                              size_t *bytes) {
+  if (!graphs || ngraphs <= 0 || !bytes) return BFS_ERR_ARG;
+  bfs_options d;
+  bfs_options_default(&d);
+  if (!o) o = &d;
+  WsLayout L{};
+  size_t off = 0;
+  layout_single(graphs, ngraphs, L, off);
+  layout_batch(graphs, ngraphs, o, L, off);
+  *bytes = off;
+  return BFS_OK;
+}
+
+bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_options *o,
+                           void *workspace, size_t ws_bytes, bfs_plan_t *out) {
+  g_create_error.clear();
+  if (!out) { g_create_error = "out is NULL"; return BFS_ERR_ARG; }
+  *out = nullptr;
+  if (!graphs || ngraphs <= 0) { g_create_error = "no graphs"; return BFS_ERR_ARG; }
+  if (!workspace || ((uintptr_t)workspace & 255)) {
+    g_create_error = "workspace must be a non-null 256-byte aligned device pointer";
+    return BFS_ERR_ARG;
+  }
+  bfs_options d;
+  bfs_options_default(&d);
+  if (!o) o = &d;
+  for (int i = 0; i < ngraphs; ++i) {
+    const bfs_graph &g = graphs[i];
+    if (g.n_global <= 0 || g.n_global >= (1ll << 31) || g.v_begin < 0 || g.v_end < g.v_begin ||
+        g.v_end > g.n_global || g.m < 0 || !g.row_ptr || (g.m > 0 && !g.col)) {
+      g_create_error = "graph " + std::to_string(i) + ": bad sizes or null pointers";
+      return BFS_ERR_ARG;
+    }
+  }
+  size_t need = 0;
+  bfs_status st = bfs_workspace_size(graphs, ngraphs, o, &need);
+  if (st) { g_create_error = "bad arguments"; return st; }
+  if (ws_bytes < need) {
+    g_create_error = "workspace too small: need " + std::to_string(need) + " bytes";
+    return BFS_ERR_WORKSPACE;
+  }
+  Plan *p = new (std::nothrow) Plan();
+  if (!p) { g_create_error = "out of host memory"; return BFS_ERR_ARG; }
+  p->graphs.assign(graphs, graphs + ngraphs);
+  p->opt = *o;
+  p->ws = workspace;
+  p->ws_bytes = ws_bytes;
+  p->stream = (hipStream_t)o->hip_stream;
+  size_t off = 0;
+  layout_single(graphs, ngraphs, p->lay, off);
+  layout_batch(graphs, ngraphs, o, p->lay, off);
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    g_create_error = "no HIP device";
+    delete p;
+    return BFS_ERR_HIP;
+  }
+  p->num_cus = prop.multiProcessorCount;
+  p->coop = prop.cooperativeLaunch;
+  int bpc = persistent_blocks_per_cu();
+  p->persist_grid = o->grid_blocks > 0 ? o->grid_blocks : p->num_cus * std::min(std::max(bpc, 1), 4);
+  if (bpc <= 0 || p->persist_grid > bpc * p->num_cus) p->coop = 0;
+  for (auto &ev : p->ev) {
+    if (hipEventCreate(&ev) != hipSuccess) {
+      g_create_error = "hipEventCreate failed";
+      delete p;
+      return BFS_ERR_HIP;
+    }
+  }
+  st = validate_graphs(p);
+  if (st) { g_create_error = p->err; delete p; return st; }
+  st = choose_tuning(p);
+  if (st) { g_create_error = p->err; delete p; return st; }
+  st = batch_init(p);
+  if (st) { g_create_error = p->err; delete p; return st; }
+  *out = p;
+  return BFS_OK;
+}
+
+void bfs_plan_destroy(bfs_plan_t p) {
+  if (!p) return;
+  batch_shutdown(p);
+  delete p;
+}
+
+const char *bfs_last_error(bfs_plan_t p) {
+  if (!p) return g_create_error.c_str();
+  return p->err.c_str();
+}
+
+bfs_status bfs_begin(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist) {
+  if (!p) return BFS_ERR_ARG;
+  if (graph < 0 || graph >= (int32_t)p->graphs.size())
+    return p->fail(BFS_ERR_ARG, "graph index out of range");
+  const bfs_graph &g = p->graphs[graph];
+  if (source < 0 || source >= g.n_global)
+    return p->fail(BFS_ERR_ARG, "source " + std::to_string(source) + " outside [0, n_global)");
+  if (!dist) return p->fail(BFS_ERR_ARG, "dist is NULL");
+  std::lock_guard<std::mutex> lk(p->run_mu);
+  p->cur_graph = graph;
+  p->cur_source = source;
+  p->cur_dist = dist;
+  p->level = 0;
+  p->level_frontier.assign(1, (source >= g.v_begin && source < g.v_end) ? 1 : 0);
+  View v = p->view(graph, dist);
+  int grid = (int)std::min<int64_t>((g.n_global + kBlock - 1) / kBlock, (int64_t)p->num_cus * 16);
+  hipError_t e = launch_reset(v, source, std::max(grid, 1), p->stream);
+  if (e != hipSuccess) { p->began = false; return p->hip_fail(e, "reset launch"); }
+  p->began = true;
+  p->finished = false;
+  return BFS_OK;
+}
+
+bfs_status bfs_expand(bfs_plan_t p, const uint64_t **local_next) {
+  if (!p) return BFS_ERR_ARG;
+  if (!p->began || p->finished) return p->fail(BFS_ERR_STATE, "bfs_expand before bfs_begin");
+  View v = p->view(p->cur_graph, p->cur_dist);
+  if (p->opt.collect_stats && p->level + 1 < kMaxStatLevels) {
+    hipError_t e = launch_clear_stats_row(v, p->level + 1, p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "stats launch");
+  }
+  hipError_t e = launch_expand(v, p->level, p->wide_grid(), p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "expand launch");
+  if (local_next) *local_next = v.next;
+  return BFS_OK;
+}
+
+bfs_status bfs_merge_frontier(bfs_plan_t p, const uint64_t *const *incoming, int32_t k,
+                              int32_t keep_next, int64_t *global_new, int64_t *owned_new) {
+  if (!p) return BFS_ERR_ARG;
+  if (!p->began || p->finished) return p->fail(BFS_ERR_STATE, "bfs_merge_frontier before bfs_begin");
+  if (k < 0 || (k > 0 && !incoming)) return p->fail(BFS_ERR_ARG, "bad incoming list");
+  for (int i = 0; i < k; ++i)
+    if (!incoming[i]) return p->fail(BFS_ERR_ARG, "incoming bitmap " + std::to_string(i) + " is NULL");
+  View v = p->view(p->cur_graph, p->cur_dist);
+  int done = 0;
+  do {
+    MergeArgs a{};
+    const int chunk = std::min(k - done, kMaxIncoming);
+    for (int i = 0; i < chunk; ++i) a.inc[i] = incoming[done + i];
+    a.k = chunk;
+    done += chunk;
+    a.keep_next = (done < k || keep_next) ? 1 : 0;
+    a.level = p->level;
+    hipError_t e = launch_merge(v, a, p->merge_grid(v.words), p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "merge launch");
+  } while (done < k);
+  if (global_new || owned_new || !keep_next) {
+    Ctl c;
+    bfs_status st = p->read_ctl(c);
+    if (st) return st;
+    if (global_new) *global_new = (int64_t)c.newcnt[p->level % 3];
+    if (owned_new) *owned_new = (int64_t)c.ownedcnt[p->level % 3];
+    if (!keep_next) {
+      if ((int)p->level_frontier.size() == p->level + 1)
+        p->level_frontier.push_back((int64_t)c.ownedcnt[p->level % 3]);
+      p->last_level_new = (int64_t)c.newcnt[p->level % 3];
+      p->level += 1;
+    }
+  }
+  return BFS_OK;
+}
+
+bfs_status bfs_finish(bfs_plan_t p, int32_t *parent, bfs_stats *st) {
+  if (!p) return BFS_ERR_ARG;
+  if (!p->began) return p->fail(BFS_ERR_STATE, "bfs_finish before bfs_begin");
+  View v = p->view(p->cur_graph, p->cur_dist);
+  if (parent) {
+    hipError_t e = launch_parent(v, parent, p->cur_source, p->wide_grid(), p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "parent launch");
+  }
+  Ctl c;
+  bfs_status s = p->read_ctl(c);
+  if (s) return s;
+  p->finished = true;
+  if (st) {
+    st->levels = p->persistent_levels > 0 ? p->persistent_levels : p->level;
+    st->reached = (int64_t)c.reached;
+    st->edges_scanned = (int64_t)c.edges;
+    st->ms = p->last_ms;
+  }
+  return BFS_OK;
+}
+
+bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, int32_t *parent,
+                   bfs_stats *st) {
+  if (!p) return BFS_ERR_ARG;
+  bfs_status s;
+  hipError_t e;
+  hipEvent_t ev0 = p->ev[0], ev1 = p->ev[1];
+  p->persistent_levels = 0;
+  p->last_ms = 0.f;
+  e = hipEventRecord(ev0, p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
+  s = bfs_begin(p, graph, source, dist);
+  if (s) return s;
+  const bfs_graph &g = p->graphs[graph];
+  const bool host_loop = p->opt.exchange != nullptr || p->opt.loop_mode == BFS_LOOP_HOST ||
+                         (p->opt.loop_mode == BFS_LOOP_AUTO && !p->coop);
+  if (p->opt.loop_mode == BFS_LOOP_PERSISTENT && (!p->coop || p->opt.exchange))
+    return p->fail(BFS_ERR_ARG, "persistent loop needs cooperative launch and no exchange callback");
+  if (!host_loop) {
+    View v = p->view(graph, dist);
+    const int max_levels = (int)std::min<int64_t>(g.n_global + 1, 1ll << 30);
+    e = launch_persistent(v, max_levels, p->persist_grid, p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "persistent launch");
+    e = hipEventRecord(ev1, p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
+    Ctl c;
+    s = p->read_ctl(c);
+    if (s) return s;
+    if (c.bar.tripped) return p->fail(BFS_ERR_DEVICE, "grid barrier spin limit exceeded");
+    if (c.err) return p->fail(BFS_ERR_DEVICE, "level limit exceeded");
+    p->persistent_levels = c.levels;
+    p->level = c.levels;
+  } else {
+    for (;;) {
+      const uint64_t *local_next = nullptr;
+      s = bfs_expand(p, &local_next);
+      if (s) return s;
+      const uint64_t *const *inc = nullptr;
+      int32_t k = 0;
+      if (p->opt.exchange) {
+        e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return p->hip_fail(e, "hipStreamSynchronize");
+        int32_t rc = p->opt.exchange(p->opt.exchange_ctx, p->level, local_next, &inc, &k);
+        if (rc != 0) return p->fail(BFS_ERR_EXCHANGE, "exchange callback returned " + std::to_string(rc));
+        if (k < 0 || (k > 0 && !inc)) return p->fail(BFS_ERR_EXCHANGE, "exchange callback gave a bad list");
+      }
+      int64_t gnew = 0;
+      s = bfs_merge_frontier(p, inc, k, 0, &gnew, nullptr);
+      if (s) return s;
+      if (gnew == 0) break;
+    }
+    e = hipEventRecord(ev1, p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
+  }
+  e = hipEventSynchronize(ev1);
+  if (e != hipSuccess) return p->hip_fail(e, "hipEventSynchronize");
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, ev0, ev1) != hipSuccess) ms = -1.f;
+  p->last_ms = ms;
+  return bfs_finish(p, parent, st);
+}
+
+bfs_status bfs_level_stats(bfs_plan_t p, int64_t *frontier, int64_t *hist, int32_t max_levels,
+                           int32_t *levels) {
+  if (!p) return BFS_ERR_ARG;
+  if (!p->opt.collect_stats) return p->fail(BFS_ERR_STATE, "plan created without collect_stats");
+  if (!p->began) return p->fail(BFS_ERR_STATE, "no traversal yet");
+  const int nl = std::min(p->level, kMaxStatLevels);
+  if (levels) *levels = nl;
+  const int cnt = std::min(nl, std::max(max_levels, 0));
+  if (cnt <= 0) return BFS_OK;
+  std::vector<int64_t> f((size_t)kMaxStatLevels);
+  std::vector<uint32_t> h((size_t)kMaxStatLevels * kNumBins);
+  hipError_t e = hipMemcpyAsync(f.data(), (char *)p->ws + p->lay.lvl_frontier,
+                                sizeof(int64_t) * kMaxStatLevels, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h.data(), (char *)p->ws + p->lay.lvl_hist,
+                       sizeof(uint32_t) * kMaxStatLevels * kNumBins, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "stats copy");
+  for (int L = 0; L < cnt; ++L) {
+    if (frontier) {
+      if (p->persistent_levels > 0 || L == 0) frontier[L] = f[L];
+      else frontier[L] = L < (int)p->level_frontier.size() ? p->level_frontier[L] : 0;
+    }
+    if (hist)
+      for (int b = 0; b < kNumBins; ++b) hist[(size_t)L * kNumBins + b] = h[(size_t)L * kNumBins + b];
+  }
+  return BFS_OK;
+}
+
+}  // extern "C"

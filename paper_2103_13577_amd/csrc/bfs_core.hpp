@@ -1,0 +1,88 @@
+// Shared host/device definitions of the single-source traversal: the control
+// block and the view of a plan's workspace passed to every kernel.
+#pragma once
+
+#include <stdint.h>
+
+#include "device.hpp"
+
+namespace bfsk {
+
+constexpr int kNumBins = 34;   // degree bin 0 (degree 0) .. 33
+constexpr int kTiers = 3;      // lane-group, wavefront, chunked workgroup
+constexpr int kBlock = 256;    // threads per workgroup for the traversal kernels
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kMaxStatLevels = 4096;
+constexpr int kHeavyShift = 40;  // packed heavy-tier counter: count << 40 | chunks
+constexpr uint64_t kChunkMask = (1ull << kHeavyShift) - 1;
+
+// Device control block at the start of the workspace.
+struct Ctl {
+  GridBarrier bar;
+  uint32_t qn[2][2];      // tier-0 and tier-1 queue lengths, by level parity
+  uint64_t heavy[2];      // tier-2 queue: (count << 40) | total chunks, by parity
+  uint64_t newcnt[3];     // vertices new in the level (all ranges), by level mod 3
+  uint64_t ownedcnt[3];   // owned vertices new in the level, by level mod 3
+  uint64_t edges;         // sum of degrees over every enqueued owned vertex
+  uint64_t reached;       // vertices with a finite distance
+  int32_t levels;         // persistent loop: number of nonempty levels
+  int32_t err;            // device-side error flags
+  uint64_t pad[3];
+};
+
+// Kernel view of a plan's workspace for one graph.
+struct View {
+  int64_t n;        // n_global
+  int64_t vb, ve;   // owned range
+  int64_t m;
+  int64_t words;    // ceil(n / 64)
+  const int64_t *rp;
+  const int32_t *col;
+  int32_t *dist;
+  uint64_t *visited;
+  uint64_t *next;
+  int32_t *q0[2];
+  int32_t *q1[2];
+  int32_t *q2[2];
+  uint32_t *cstart[2];
+  Ctl *ctl;
+  int64_t *lvl_frontier;  // [kMaxStatLevels]
+  uint32_t *lvl_hist;     // [kMaxStatLevels * kNumBins]
+  int32_t small_bin;      // bins < small_bin -> tier 0
+  int32_t wave_bin;       // bins < wave_bin -> tier 1, else tier 2
+  int32_t chunk_shift;    // tier-2 work item = 2^chunk_shift edges
+  int32_t stats;
+};
+
+constexpr int kMaxIncoming = 8;  // received bitmaps per merge launch
+
+struct MergeArgs {
+  const uint64_t *inc[kMaxIncoming];  // received bitmaps (device)
+  int32_t k;
+  int32_t keep_next;
+  int32_t level;
+};
+
+// Degree bin: 0 for degree 0, else 1 + floor(log2(degree)).
+__host__ __device__ __forceinline__ int degree_bin(int64_t d) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return d <= 0 ? 0 : 64 - __clzll((unsigned long long)d);
+#else
+  return d <= 0 ? 0 : 64 - __builtin_clzll((unsigned long long)d);
+#endif
+}
+
+__host__ __device__ __forceinline__ int tier_of_bin(int b, int small_bin, int wave_bin) {
+  return b < small_bin ? 0 : (b < wave_bin ? 1 : 2);
+}
+
+// Host launchers (bfs_kernels.hip).
+hipError_t launch_reset(const View &v, int64_t src, int grid, hipStream_t s);
+hipError_t launch_expand(const View &v, int level, int grid, hipStream_t s);
+hipError_t launch_merge(const View &v, const MergeArgs &a, int grid, hipStream_t s);
+hipError_t launch_clear_stats_row(const View &v, int level, hipStream_t s);
+hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, hipStream_t s);
+hipError_t launch_persistent(const View &v, int max_levels, int grid, hipStream_t s);
+int persistent_blocks_per_cu();
+
+}  // namespace bfsk

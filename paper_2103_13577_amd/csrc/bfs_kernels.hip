@@ -1,0 +1,517 @@
+// Single-source top-down traversal kernels for gfx950.
+//
+// Phases (Algorithm 2 of the paper; Algorithm 1 is the one-node case):
+//   reset   - every distance to infinity, the root to 0 and into the owned
+//             frontier if owned (Algorithm 2 set-up).
+//   expand  - Phase 1: each owned frontier vertex scans its adjacency; every
+//             neighbour not yet visited is marked in the node's next-frontier
+//             bitmap with a device-scope atomic OR (the atomic enqueue of
+//             Algorithm 2). Work is split by degree tier (logarithmic radix
+//             binning, Section 4 "Load Balanced Traversals"):
+//               tier 0: small degrees, 64 vertices per wavefront with their
+//                       edges spread evenly over the lanes;
+//               tier 1: medium degrees, one wavefront per vertex;
+//               tier 2: large degrees, fixed-size edge chunks, one workgroup
+//                       per chunk (a hub is spread over many workgroups).
+//   merge   - Phase 2: OR of the local bitmap with k received bitmaps,
+//             new = merged & ~visited, distance level+1 for every new vertex,
+//             owned new vertices compacted (ballot/popcount) straight into
+//             the next level's tier queues.
+// The same phase functions run either one launch per phase (host-driven
+// loop) or inside one cooperative launch with grid barriers between phases.
+
+#include <hip/hip_runtime.h>
+
+#include "bfs_core.hpp"
+
+namespace bfsk {
+
+// ---------------------------------------------------------------------------
+// reset
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kBlock) k_reset(View v, int64_t src) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = tid; i < v.n; i += stride) v.dist[i] = (i == src) ? 0 : -1;
+  const int64_t sw = src >> 6;
+  for (int64_t i = tid; i < v.words; i += stride) {
+    v.visited[i] = (i == sw) ? (1ull << (src & 63)) : 0ull;
+    v.next[i] = 0ull;
+  }
+  if (tid == 0) {
+    Ctl *c = v.ctl;
+    c->bar.count = 0;
+    c->bar.gen = 0;
+    c->bar.tripped = 0;
+    c->qn[0][0] = c->qn[0][1] = c->qn[1][0] = c->qn[1][1] = 0;
+    c->heavy[0] = c->heavy[1] = 0;
+    for (int k = 0; k < 3; ++k) c->newcnt[k] = c->ownedcnt[k] = 0;
+    c->edges = 0;
+    c->reached = 1;
+    c->levels = 0;
+    c->err = 0;
+    const bool owned = src >= v.vb && src < v.ve;
+    int64_t deg = 0;
+    if (owned) {
+      const int64_t li = src - v.vb;
+      deg = v.rp[li + 1] - v.rp[li];
+      const int b = degree_bin(deg);
+      const int t = tier_of_bin(b, v.small_bin, v.wave_bin);
+      if (deg > 0) {
+        if (t == 0) { v.q0[0][0] = (int32_t)src; c->qn[0][0] = 1; }
+        else if (t == 1) { v.q1[0][0] = (int32_t)src; c->qn[0][1] = 1; }
+        else {
+          v.q2[0][0] = (int32_t)src;
+          v.cstart[0][0] = 0;
+          const uint64_t nch = (uint64_t)((deg + (1ll << v.chunk_shift) - 1) >> v.chunk_shift);
+          c->heavy[0] = (1ull << kHeavyShift) | nch;
+        }
+      }
+      c->edges = (uint64_t)deg;
+    }
+    if (v.stats) {
+      v.lvl_frontier[0] = owned ? 1 : 0;
+      for (int b = 0; b < kNumBins; ++b) v.lvl_hist[b] = 0;
+      if (owned) v.lvl_hist[degree_bin(deg)] = 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// expand (Phase 1)
+// ---------------------------------------------------------------------------
+
+// Marks u in the next-frontier bitmap unless it is already visited. The
+// visited test is a plain load (visited does not change during expansion);
+// the cached read of `next` skips most redundant atomics.
+__device__ __forceinline__ void probe(const View &v, int32_t u) {
+  const uint32_t w = (uint32_t)u >> 6;
+  const uint64_t bit = 1ull << (u & 63);
+  if (v.visited[w] & bit) return;
+  if (v.next[w] & bit) return;
+  atomic_or_noret(v.next + w, bit);
+}
+
+// Streams adjacency entries with a non-temporal hint so the bitmaps keep
+// their place in L2.
+__device__ __forceinline__ int32_t load_col(const int32_t *col, int64_t e) {
+  return __builtin_nontemporal_load(col + e);
+}
+
+// Largest s in [0, n) with a[s] <= key (a ascending, a[0] == 0 <= key).
+__device__ __forceinline__ uint32_t upper_slot(const uint32_t *a, uint32_t n, uint64_t key) {
+  uint32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi + 1) >> 1;
+    if ((uint64_t)a[mid] <= key) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Expansion of level `level` by virtual block `vb_id` of `nvb` blocks.
+__device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t nvb) {
+  __shared__ int64_t s_lo, s_hi;
+  const int cur = level & 1;
+  const int lane = lane_id();
+  const uint32_t wave = threadIdx.x / kWave;
+  const uint64_t gwave = (uint64_t)vb_id * kWavesPerBlock + wave;
+  const uint64_t nwaves = (uint64_t)nvb * kWavesPerBlock;
+
+  // Tier 2: fixed-size edge chunks of heavy vertices, one workgroup each.
+  const uint64_t hv = load_relaxed64(&v.ctl->heavy[cur]);
+  const uint32_t n2 = (uint32_t)(hv >> kHeavyShift);
+  const uint64_t nch = hv & kChunkMask;
+  for (uint64_t c = vb_id; c < nch; c += nvb) {
+    if (threadIdx.x == 0) {
+      const uint32_t s = upper_slot(v.cstart[cur], n2, c);
+      const int32_t x = v.q2[cur][s];
+      const int64_t li = x - v.vb;
+      const int64_t b = v.rp[li], e = v.rp[li + 1];
+      const int64_t lo = b + ((int64_t)(c - v.cstart[cur][s]) << v.chunk_shift);
+      s_lo = lo;
+      s_hi = min(e, lo + (1ll << v.chunk_shift));
+    }
+    __syncthreads();
+    const int64_t lo = s_lo, hi = s_hi;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += kBlock) probe(v, load_col(v.col, e));
+    __syncthreads();
+  }
+
+  // Tier 1: one wavefront per vertex.
+  const uint32_t n1 = load_relaxed32(&v.ctl->qn[cur][1]);
+  for (uint64_t i = gwave; i < n1; i += nwaves) {
+    const int64_t li = v.q1[cur][i] - v.vb;
+    const int64_t b = v.rp[li], e = v.rp[li + 1];
+    for (int64_t k = b + lane; k < e; k += kWave) probe(v, load_col(v.col, k));
+  }
+
+  // Tier 0: 64 vertices per wavefront, their edges dealt evenly to the lanes.
+  const uint32_t n0 = load_relaxed32(&v.ctl->qn[cur][0]);
+  for (uint64_t base = gwave * kWave; base < n0; base += nwaves * kWave) {
+    const uint64_t i = base + lane;
+    int64_t start = 0, deg = 0;
+    if (i < n0) {
+      const int64_t li = v.q0[cur][i] - v.vb;
+      start = v.rp[li];
+      deg = v.rp[li + 1] - start;
+    }
+    const int64_t incl = wave_incl_scan(deg);
+    const int64_t total = shfl64(incl, kWave - 1);
+    const int64_t excl = incl - deg;
+    // Every lane runs every step (the shuffles read all lanes); edge e of the
+    // wavefront's batch belongs to the first lane k with incl[k] > e.
+    for (int64_t e0 = 0; e0 < total; e0 += kWave) {
+      const int64_t e = e0 + lane;
+      int k = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const int64_t val = shfl64(incl, k + step - 1);
+        if (val <= e) k += step;
+      }
+      k = min(k, kWave - 1);
+      const int64_t xk = shfl64(excl, k);
+      const int64_t sk = shfl64(start, k);
+      if (e < total) probe(v, load_col(v.col, sk + (e - xk)));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// merge (Phase 2)
+// ---------------------------------------------------------------------------
+
+// Bits of word w that fall in the owned range [vb, ve).
+__device__ __forceinline__ uint64_t owned_mask(int64_t w, int64_t vb, int64_t ve) {
+  const int64_t lo = w * 64, hi = lo + 64;
+  if (hi <= vb || lo >= ve) return 0ull;
+  uint64_t m = ~0ull;
+  if (vb > lo) m &= ~0ull << (vb - lo);
+  if (ve < hi) m &= ~0ull >> (hi - ve);
+  return m;
+}
+
+__device__ void merge_phase(const View &v, const MergeArgs &a, uint32_t vb_id, uint32_t nvb) {
+  __shared__ uint32_t s_cnt[kWavesPerBlock][3];
+  __shared__ uint64_t s_chunks[kWavesPerBlock];
+  __shared__ uint32_t s_base[3];
+  __shared__ uint64_t s_cbase;
+  __shared__ uint32_t s_hist[kNumBins];
+  __shared__ uint64_t s_red[2][kWavesPerBlock];
+
+  const int L = a.level;
+  const int cur = L & 1, nxt = cur ^ 1;
+  const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  const int32_t dnew = L + 1;
+  const int cs = v.chunk_shift;
+
+  if (vb_id == 0 && threadIdx.x == 0) {
+    // The current level's queues are consumed; clear them for level L+2 and
+    // the new-vertex counters of level L+1.
+    v.ctl->qn[cur][0] = 0;
+    v.ctl->qn[cur][1] = 0;
+    v.ctl->heavy[cur] = 0;
+    v.ctl->newcnt[(L + 1) % 3] = 0;
+    v.ctl->ownedcnt[(L + 1) % 3] = 0;
+  }
+  if (v.stats) {
+    for (int b = threadIdx.x; b < kNumBins; b += kBlock) s_hist[b] = 0;
+    __syncthreads();
+  }
+
+  uint64_t my_new = 0, my_edges = 0, my_owned = 0;
+  const int64_t group = (int64_t)kBlock;  // words per workgroup step
+  for (int64_t g0 = (int64_t)vb_id * group; g0 < v.words; g0 += (int64_t)nvb * group) {
+    const int64_t wbase = g0 + wave * kWave;  // first word of this wavefront
+    const int64_t w = wbase + lane;
+    uint64_t nw = 0, om = 0;
+    if (w < v.words) {
+      const uint64_t nx = v.next[w];
+      uint64_t m = nx;
+      for (int j = 0; j < a.k; ++j) m |= a.inc[j][w];
+      const uint64_t vis = v.visited[w];
+      nw = m & ~vis;
+      if (nw) v.visited[w] = vis | nw;
+      if (a.keep_next) {
+        if (m != nx) v.next[w] = m;
+      } else if (nx) {
+        v.next[w] = 0ull;
+      }
+      if (w == v.words - 1 && (v.n & 63)) nw &= ~0ull >> (64 - (v.n & 63));
+      om = nw & owned_mask(w, v.vb, v.ve);
+    }
+    my_new += (uint64_t)__popcll(nw);
+
+    // Pass 1: distances of new vertices; degree tier of owned new vertices.
+    uint64_t t1m = 0, t2m = 0;
+    uint64_t chunks = 0;  // wave-uniform
+    uint64_t act = ballot(nw != 0);
+    while (act) {
+      const int j = __ffsll((unsigned long long)act) - 1;
+      act &= act - 1;
+      const uint64_t wj = readlane64(nw, j);
+      const uint64_t oj = readlane64(om, j);
+      const int64_t vtx = (wbase + j) * 64 + lane;
+      if ((wj >> lane) & 1ull) v.dist[vtx] = dnew;
+      int t = 0;
+      int64_t deg = 0;
+      const bool own = (oj >> lane) & 1ull;
+      if (own) {
+        const int64_t li = vtx - v.vb;
+        deg = v.rp[li + 1] - v.rp[li];
+        const int b = degree_bin(deg);
+        t = tier_of_bin(b, v.small_bin, v.wave_bin);
+        my_edges += (uint64_t)deg;
+        if (v.stats) atomicAdd(&s_hist[b], 1u);
+      }
+      const uint64_t m1 = ballot(own && t == 1);
+      const uint64_t m2 = ballot(own && t == 2);
+      if (lane == j) { t1m = m1; t2m = m2; }
+      if (m2) {
+        const uint64_t nc = (own && t == 2) ? (uint64_t)((deg + (1ll << cs) - 1) >> cs) : 0ull;
+        chunks += (uint64_t)wave_sum((int64_t)nc);
+      }
+    }
+    const uint32_t c0 = wave_sum_u32((uint32_t)__popcll(om & ~t1m & ~t2m));
+    const uint32_t c1 = wave_sum_u32((uint32_t)__popcll(t1m));
+    const uint32_t c2 = wave_sum_u32((uint32_t)__popcll(t2m));
+    my_owned += (lane == 0) ? (uint64_t)(c0 + c1 + c2) : 0ull;
+
+    // Workgroup aggregation: one atomic per tier per workgroup step.
+    if (lane == 0) {
+      s_cnt[wave][0] = c0;
+      s_cnt[wave][1] = c1;
+      s_cnt[wave][2] = c2;
+      s_chunks[wave] = chunks;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t t0 = 0, t1 = 0, t2 = 0;
+      uint64_t ch = 0;
+      for (int x = 0; x < kWavesPerBlock; ++x) {
+        t0 += s_cnt[x][0];
+        t1 += s_cnt[x][1];
+        t2 += s_cnt[x][2];
+        ch += s_chunks[x];
+      }
+      s_base[0] = t0 ? atomic_add32(&v.ctl->qn[nxt][0], t0) : 0u;
+      s_base[1] = t1 ? atomic_add32(&v.ctl->qn[nxt][1], t1) : 0u;
+      if (t2) {
+        const uint64_t old =
+            atomic_add64(&v.ctl->heavy[nxt], ((uint64_t)t2 << kHeavyShift) | ch);
+        s_base[2] = (uint32_t)(old >> kHeavyShift);
+        s_cbase = old & kChunkMask;
+      } else {
+        s_base[2] = 0;
+        s_cbase = 0;
+      }
+    }
+    __syncthreads();
+    uint32_t b0 = s_base[0], b1 = s_base[1], b2 = s_base[2];
+    uint64_t cb = s_cbase;
+    for (int x = 0; x < wave; ++x) {
+      b0 += s_cnt[x][0];
+      b1 += s_cnt[x][1];
+      b2 += s_cnt[x][2];
+      cb += s_chunks[x];
+    }
+
+    // Pass 2: write owned new vertices into the level L+1 tier queues.
+    act = ballot(om != 0);
+    while (act) {
+      const int j = __ffsll((unsigned long long)act) - 1;
+      act &= act - 1;
+      const uint64_t oj = readlane64(om, j);
+      const uint64_t m1 = readlane64(t1m, j);
+      const uint64_t m2 = readlane64(t2m, j);
+      const uint64_t m0 = oj & ~m1 & ~m2;
+      const int32_t vtx = (int32_t)((wbase + j) * 64 + lane);
+      if ((m0 >> lane) & 1ull) v.q0[nxt][b0 + rank_below(m0)] = vtx;
+      if ((m1 >> lane) & 1ull) v.q1[nxt][b1 + rank_below(m1)] = vtx;
+      b0 += (uint32_t)__popcll(m0);
+      b1 += (uint32_t)__popcll(m1);
+      if (m2) {
+        const bool mine = (m2 >> lane) & 1ull;
+        int64_t nc = 0;
+        if (mine) {
+          const int64_t li = vtx - v.vb;
+          const int64_t deg = v.rp[li + 1] - v.rp[li];
+          nc = (deg + (1ll << cs) - 1) >> cs;
+        }
+        const int64_t incl = wave_incl_scan(nc);
+        if (mine) {
+          const uint32_t slot = b2 + rank_below(m2);
+          v.q2[nxt][slot] = vtx;
+          v.cstart[nxt][slot] = (uint32_t)(cb + (uint64_t)(incl - nc));
+        }
+        b2 += (uint32_t)__popcll(m2);
+        cb += (uint64_t)shfl64(incl, kWave - 1);
+      }
+    }
+    __syncthreads();  // s_cnt / s_base reuse
+  }
+
+  // Level totals: one atomic per workgroup.
+  const uint64_t wn = (uint64_t)wave_sum((int64_t)my_new);
+  const uint64_t we = (uint64_t)wave_sum((int64_t)my_edges);
+  if (lane == 0) {
+    s_red[0][wave] = wn;
+    s_red[1][wave] = we;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t tn = 0, te = 0;
+    for (int x = 0; x < kWavesPerBlock; ++x) { tn += s_red[0][x]; te += s_red[1][x]; }
+    if (tn) {
+      atomic_add64(&v.ctl->newcnt[L % 3], tn);
+      atomic_add64(&v.ctl->reached, tn);
+    }
+    if (te) atomic_add64(&v.ctl->edges, te);
+  }
+  const uint64_t wo = (uint64_t)wave_sum((int64_t)my_owned);
+  __syncthreads();
+  if (lane == 0) s_red[0][wave] = wo;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t to = 0;
+    for (int x = 0; x < kWavesPerBlock; ++x) to += s_red[0][x];
+    if (to) atomic_add64(&v.ctl->ownedcnt[L % 3], to);
+  }
+  if (v.stats && L + 1 < kMaxStatLevels) {
+    __syncthreads();
+    for (int b = threadIdx.x; b < kNumBins; b += kBlock)
+      if (s_hist[b]) atomic_add32(&v.lvl_hist[(L + 1) * kNumBins + b], s_hist[b]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kBlock) k_expand(View v, int level) {
+  expand_phase(v, level, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_merge(View v, MergeArgs a) {
+  merge_phase(v, a, blockIdx.x, gridDim.x);
+}
+
+// Clears the stats row of a level before its merge (host-driven loop).
+__global__ void k_clear_stats_row(View v, int level) {
+  if (level < kMaxStatLevels)
+    for (int b = threadIdx.x; b < kNumBins; b += blockDim.x) v.lvl_hist[level * kNumBins + b] = 0;
+}
+
+// Whole traversal in one cooperative launch: expand, barrier, merge, barrier,
+// until a level finds no new vertex. Every block runs the same number of
+// barriers; the loop also stops if a barrier tripped its spin limit.
+__global__ void __launch_bounds__(kBlock) k_persistent(View v, int max_levels) {
+  uint32_t gen = 0;
+  const uint32_t nb = gridDim.x;
+  MergeArgs a;
+  a.k = 0;
+  a.keep_next = 0;
+  int L = 0;
+  for (;; ++L) {
+    if (v.stats && L + 1 < kMaxStatLevels) {
+      if (blockIdx.x == 0)
+        for (int b = threadIdx.x; b < kNumBins; b += blockDim.x)
+          v.lvl_hist[(L + 1) * kNumBins + b] = 0;
+    }
+    expand_phase(v, L, blockIdx.x, nb);
+    grid_barrier(&v.ctl->bar, nb, gen);
+    a.level = L;
+    merge_phase(v, a, blockIdx.x, nb);
+    grid_barrier(&v.ctl->bar, nb, gen);
+    const uint64_t nn = load_relaxed64(&v.ctl->newcnt[L % 3]);
+    if (v.stats && blockIdx.x == 0 && threadIdx.x == 0 && L + 1 < kMaxStatLevels)
+      v.lvl_frontier[L + 1] = (int64_t)load_relaxed64(&v.ctl->ownedcnt[L % 3]);
+    const int tripped = __hip_atomic_load(&v.ctl->bar.tripped, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    if (nn == 0 || tripped || L + 1 >= max_levels) break;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    v.ctl->levels = L + 1;
+    if (L + 1 >= max_levels) v.ctl->err |= 2;
+  }
+}
+
+// Canonical parents for the owned range: one wavefront per owned vertex takes
+// the smallest neighbour one level closer to the root. Non-owned reached
+// vertices get -2, unreached -1, the root itself.
+__global__ void __launch_bounds__(kBlock) k_parent(View v, int32_t *parent, int64_t src) {
+  const int lane = lane_id();
+  const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t x = gw; x < v.n; x += nw) {
+    const int32_t d = v.dist[x];
+    int32_t out;
+    if (d < 0) out = -1;
+    else if (x == src) out = (int32_t)x;
+    else if (x < v.vb || x >= v.ve) out = -2;
+    else {
+      const int64_t li = x - v.vb;
+      int32_t best = 0x7fffffff;
+      for (int64_t e = v.rp[li] + lane; e < v.rp[li + 1]; e += kWave) {
+        const int32_t u = v.col[e];
+        if (u < best && v.dist[u] == d - 1) best = u;
+      }
+#pragma unroll
+      for (int s = 32; s >= 1; s >>= 1) best = min(best, __shfl_xor(best, s));
+      out = best;
+    }
+    if (lane == 0) parent[x] = out;
+  }
+}
+
+}  // namespace bfsk
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+namespace bfsk {
+
+hipError_t launch_reset(const View &v, int64_t src, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3(grid), dim3(kBlock), 0, s, v, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const View &v, int level, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_expand, dim3(grid), dim3(kBlock), 0, s, v, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge(const View &v, const MergeArgs &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_merge, dim3(grid), dim3(kBlock), 0, s, v, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_stats_row(const View &v, int level, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_stats_row, dim3(1), dim3(64), 0, s, v, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_parent, dim3(grid), dim3(kBlock), 0, s, v, parent, src);
+  return hipGetLastError();
+}
+
+// Co-resident blocks per CU for the persistent kernel.
+int persistent_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent, kBlock, 0) != hipSuccess)
+    return 0;
+  return nb;
+}
+
+hipError_t launch_persistent(const View &v, int max_levels, int grid, hipStream_t s) {
+  View vv = v;
+  int ml = max_levels;
+  void *args[] = {&vv, &ml};
+  return hipLaunchCooperativeKernel((const void *)k_persistent, dim3(grid), dim3(kBlock), args, 0,
+                                    s);
+}
+
+}  // namespace bfsk

@@ -1,0 +1,126 @@
+// Device-side building blocks for gfx950 (CDNA4, 64-lane wavefronts):
+// wavefront ballot/scan helpers, device-scope atomics and a bounded grid
+// barrier for cooperative (co-resident) launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bfsk {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// 64-bit ballot of a per-lane predicate.
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Number of set bits of `mask` below this lane (exclusive rank).
+__device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
+  uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, l);
+  uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int64_t shfl64(int64_t x, int src) {
+  int lo = __shfl((int)(uint32_t)(uint64_t)x, src);
+  int hi = __shfl((int)(uint32_t)((uint64_t)x >> 32), src);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Inclusive prefix sum across the wavefront (Hillis-Steele over 6 steps).
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t x) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    int64_t y = shfl64(x, l >= d ? l - d : l);
+    if (l >= d) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += shfl64(x, lane_id() ^ d);
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += (uint32_t)__shfl_xor((int)x, d);
+  return x;
+}
+
+// Relaxed device-scope atomics (agent scope: every CU of every XCD).
+__device__ __forceinline__ void atomic_or_noret(uint64_t *p, uint64_t v) {
+  (void)__hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t atomic_or64(uint64_t *p, uint64_t v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t atomic_add32(uint32_t *p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t atomic_add64(uint64_t *p, uint64_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_relaxed32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t load_relaxed64(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t load_relaxed_i32(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier state. `count` and `gen` start at 0 before a cooperative launch
+// (the reset kernel clears them); every block keeps its own generation.
+struct GridBarrier {
+  uint32_t count;
+  uint32_t gen;
+  int32_t tripped;  // set when a wait exceeded its spin limit
+  uint32_t pad;
+};
+
+// Spin limit per barrier wait: ~2^22 sleeps of 64 clocks is ~0.1 s at 2.4 GHz,
+// orders of magnitude above any legitimate wait for co-resident blocks.
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+// All blocks of a cooperative launch must call this the same number of times.
+// Release/acquire at agent scope make every write before the barrier visible
+// to every read after it. If a wait exceeds the spin limit the barrier marks
+// `tripped` and lets the block continue, so the kernel always terminates; the
+// host reports the trip as an error.
+__device__ __forceinline__ void grid_barrier(GridBarrier *b, uint32_t nblocks, uint32_t &gen) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t target = gen + 1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    uint32_t arrived =
+        __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    if (arrived == nblocks) {
+      __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&b->gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(&b->tripped, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  gen += 1;
+  __syncthreads();
+}
+
+}  // namespace bfsk

@@ -1,0 +1,83 @@
+// Plan set-up: input validation on the device, tier thresholds, and the
+// stubs that batched execution fills in.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+
+#include "plan.hpp"
+
+namespace bfsk {
+
+// Flags: 1 = row_ptr[0] != 0, 2 = row_ptr decreasing, 4 = row_ptr[last] != m,
+// 8 = column id outside [0, n_global).
+__global__ void k_validate(const int64_t *rp, int64_t nrows, const int32_t *col, int64_t m,
+                           int64_t n_global, int32_t *flags) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int32_t f = 0;
+  if (tid == 0) {
+    if (rp[0] != 0) f |= 1;
+    if (rp[nrows] != m) f |= 4;
+  }
+  for (int64_t i = tid; i < nrows; i += stride)
+    if (rp[i + 1] < rp[i]) f |= 2;
+  for (int64_t e = tid; e < m; e += stride) {
+    const int32_t u = col[e];
+    if (u < 0 || (int64_t)u >= n_global) f |= 8;
+  }
+  if (f) atomicOr(flags, f);
+}
+
+bfs_status validate_graphs(Plan *p) {
+  int32_t *flag = (int32_t *)((char *)p->ws + p->lay.ctl);  // scratch before any run
+  for (size_t i = 0; i < p->graphs.size(); ++i) {
+    const bfs_graph &g = p->graphs[i];
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int32_t), p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "hipMemsetAsync");
+    const int grid = p->num_cus * 8;
+    hipLaunchKernelGGL(k_validate, dim3(grid), dim3(256), 0, p->stream, g.row_ptr,
+                       g.v_end - g.v_begin, g.col, g.m, g.n_global, flag);
+    e = hipGetLastError();
+    if (e != hipSuccess) return p->hip_fail(e, "validate launch");
+    int32_t h = 0;
+    e = hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "validate readback");
+    if (h) {
+      std::string why;
+      if (h & 1) why += " row_ptr[0]!=0";
+      if (h & 2) why += " row_ptr decreasing";
+      if (h & 4) why += " row_ptr[last]!=m";
+      if (h & 8) why += " column id out of range";
+      return p->fail(BFS_ERR_ARG, "graph " + std::to_string(i) + " invalid:" + why);
+    }
+  }
+  return BFS_OK;
+}
+
+bfs_status choose_tuning(Plan *p) {
+  p->tune.assign(p->graphs.size(), Tuning{});
+  for (size_t i = 0; i < p->graphs.size(); ++i) {
+    Tuning &t = p->tune[i];
+    if (p->opt.small_bin > 0) t.small_bin = p->opt.small_bin;
+    if (p->opt.wave_bin > 0) t.wave_bin = p->opt.wave_bin;
+    if (p->opt.chunk_edges > 0) {
+      int s = 0;
+      while ((1 << s) < p->opt.chunk_edges && s < 30) ++s;
+      t.chunk_shift = s;
+    }
+    if (t.small_bin < 1 || t.wave_bin < t.small_bin || t.chunk_shift < 6)
+      return p->fail(BFS_ERR_ARG, "bad tier thresholds");
+    // cstart entries are 32-bit: total chunks must stay below 2^32.
+    const int64_t m = p->graphs[i].m;
+    if ((m >> t.chunk_shift) + (p->graphs[i].v_end - p->graphs[i].v_begin) >= (1ll << 32))
+      return p->fail(BFS_ERR_ARG, "chunk_edges too small for this graph");
+    if (p->graphs[i].v_end - p->graphs[i].v_begin >= (1ll << (64 - kHeavyShift)))
+      return p->fail(BFS_ERR_ARG, "owned range too large");
+  }
+  return BFS_OK;
+}
+
+}  // namespace bfsk

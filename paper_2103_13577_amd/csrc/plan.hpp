@@ -1,0 +1,95 @@
+// Host-side plan object behind the opaque bfs_plan_t handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/bfs.h"
+#include "bfs_core.hpp"
+
+namespace bfsk {
+
+// Byte offsets of the workspace regions.
+struct WsLayout {
+  size_t ctl, lvl_frontier, lvl_hist, visited, next;
+  size_t q[3][2];
+  size_t cstart[2];
+  // batched multi-source state (per graph)
+  std::vector<size_t> ms_front, ms_next, ms_seen;  // uint64[n_g * lanes] each
+  std::vector<size_t> ms_queue[2];                 // int32[n_g] active-vertex queues
+  size_t ms_ctl = 0;                               // per-graph control blocks
+  size_t ms_dirty = 0;
+};
+
+// Tier thresholds per graph (degree bins; see bfs_core.hpp).
+struct Tuning {
+  int32_t small_bin = 6;     // degree < 32 -> lane-group tier
+  int32_t wave_bin = 13;     // degree < 4096 -> wavefront tier
+  int32_t chunk_shift = 12;  // 4096-edge chunks for the workgroup tier
+};
+
+struct BatchState;  // batched / serving state (msbfs.hip)
+
+}  // namespace bfsk
+
+struct bfs_plan_s {
+  std::vector<bfs_graph> graphs;
+  bfs_options opt{};
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  bfsk::WsLayout lay{};
+  std::vector<bfsk::Tuning> tune;
+  int num_cus = 0;
+  int coop = 0;
+  int persist_grid = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::string err;
+
+  // single-source traversal state
+  std::mutex run_mu;
+  bool began = false, finished = false;
+  int32_t cur_graph = 0;
+  int64_t cur_source = 0;
+  int32_t *cur_dist = nullptr;
+  int32_t level = 0;
+  int32_t persistent_levels = 0;
+  int64_t last_level_new = 0;
+  float last_ms = 0.f;
+  std::vector<int64_t> level_frontier;
+
+  bfsk::BatchState *batch = nullptr;
+
+  bfs_status fail(bfs_status st, const std::string &msg);
+  bfs_status hip_fail(hipError_t e, const char *what);
+  bfsk::View view(int32_t gi, int32_t *dist) const;
+  int wide_grid() const;
+  int merge_grid(int64_t words) const;
+  bfs_status read_ctl(bfsk::Ctl &c);
+
+  ~bfs_plan_s() {
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+namespace bfsk {
+using Plan = bfs_plan_s;
+
+void layout_single(const bfs_graph *g, int32_t ng, WsLayout &L, size_t &off);
+void layout_batch(const bfs_graph *g, int32_t ng, const bfs_options *o, WsLayout &L, size_t &off);
+bfs_status validate_graphs(Plan *p);
+bfs_status choose_tuning(Plan *p);
+bfs_status batch_init(Plan *p);
+void batch_shutdown(Plan *p);
+}  // namespace bfsk

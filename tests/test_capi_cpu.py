@@ -1,0 +1,49 @@
+"""The C ABI library loads and exports every entry point bfs.h declares
+(no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2103_13577_amd as pkg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "bfs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bfs_[a-z_]+)\s*\(", src)) - {"bfs_exchange_fn"})
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("libbfs.so not built")
+    lib = ctypes.CDLL(pkg.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(pkg.EXPORTED)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(pkg, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(pkg, "_lib", None)
+    with pytest.raises(ImportError):
+        pkg.lib()
+
+
+def test_create_error_without_device():
+    """Argument errors are reported through status codes, not exceptions."""
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("libbfs.so not built")
+    L = pkg.lib()
+    h = ctypes.c_void_p(0)
+    g = pkg.bfs_graph(0, 0, 0, 0, 0, 0)
+    st = L.bfs_plan_create(ctypes.byref(g), 1, None, 256, 1 << 20, ctypes.byref(h))
+    assert st == 1 and not h.value
+    assert b"bad sizes" in L.bfs_last_error(None)
+    sz = ctypes.c_size_t(0)
+    assert L.bfs_workspace_size(None, 0, None, ctypes.byref(sz)) == 1

@@ -1,0 +1,342 @@
+"""GPU parity of the single-source path against the CPU oracle (through the C ABI).
+
+Distances are integers: the bar is bit-exact equality with the oracle on
+every vertex. Parents are compared with the oracle's canonical parent.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_2103_13577_amd as pkg
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(g, src, gpu, parent=False, **opts):
+    import torch
+    dg = pkg.DeviceGraph.from_csr(g, gpu)
+    plan = pkg.Plan([dg], **opts)
+    dist, par, st = plan.run(0, src, parent=parent)
+    torch.cuda.synchronize()
+    out = dist.cpu().numpy(), (par.cpu().numpy() if par is not None else None), st
+    plan.close()
+    return out
+
+
+SMALL_GRAPHS = [
+    ("path", lambda: gg.path_graph(300), [0, 150, 299]),
+    ("cycle", lambda: gg.cycle_graph(257), [0, 100]),
+    ("star", lambda: gg.star_graph(5000), [0, 17]),
+    ("complete", lambda: gg.complete_graph(130), [3]),
+    ("grid", lambda: gg.grid(97, 61, 0.0, seed=1), [0, 3000]),
+    ("grid_del", lambda: gg.grid(128, 128, 0.02, seed=2), [5, 9000]),
+    ("hypercube", lambda: gg.hypercube_graph(12), [0, 1234]),
+    ("lollipop", lambda: gg.lollipop_graph(64, 300), [0, 363]),
+    ("union", lambda: gg.disjoint_union(gg.star_graph(100), gg.path_graph(70)), [0, 120]),
+    ("empty", lambda: gg.empty_graph(100), [7]),
+    ("single", lambda: gg.empty_graph(1), [0]),
+]
+
+MODES = [dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST),
+         # tiny thresholds push vertices into the wavefront and chunked tiers
+         dict(loop_mode=pkg.LOOP_PERSISTENT, small_bin=2, wave_bin=4, chunk_edges=64),
+         dict(loop_mode=pkg.LOOP_HOST, small_bin=1, wave_bin=1, chunk_edges=64)]
+
+
+@pytest.mark.parametrize("name,make,sources", SMALL_GRAPHS, ids=[x[0] for x in SMALL_GRAPHS])
+@pytest.mark.parametrize("mode", range(len(MODES)))
+def test_small_graphs_exact(gpu, name, make, sources, mode):
+    g = make()
+    for s in sources:
+        print(f"[gpu] {name} src={s} mode={MODES[mode]}", flush=True)
+        d, p, st = _run(g, s, gpu, parent=True, **MODES[mode])
+        ref = oracle.bfs(g, s)
+        assert np.array_equal(d, ref)
+        assert np.array_equal(p, oracle.parent(g, ref))
+        assert st.reached == int((ref >= 0).sum())
+        assert st.levels == int(ref.max()) + 1
+        assert st.edges_scanned == oracle.edges_scanned(g, ref)
+
+
+@pytest.mark.parametrize("mode", range(len(MODES)))
+def test_rmat_scale14_64_sources(gpu, mode):
+    """R-MAT scale 14, edge factor 8: 64 seeded sources, one plan reused."""
+    import torch
+    g = gg.rmat(14, 8, seed=0x5EED0014, perm_seed=0xBEEF0014)
+    srcs = gg.pick_sources(g, 64, seed=0xC0FFEE14)
+    dg = pkg.DeviceGraph.from_csr(g, gpu)
+    plan = pkg.Plan([dg], **MODES[mode])
+    dist = torch.empty(g.n, dtype=torch.int32, device=gpu)
+    print(f"[gpu] rmat14 64 sources mode={MODES[mode]}", flush=True)
+    for s in srcs:
+        plan.run(0, int(s), dist=dist)
+        assert np.array_equal(dist.cpu().numpy(), oracle.bfs(g, int(s))), int(s)
+    plan.close()
+
+
+def test_rmat_scale18_ef16_tiers(gpu):
+    """Hubs large enough for the chunked workgroup tier with default bins."""
+    g = gg.rmat(18, 16, seed=77, perm_seed=78)
+    for s in gg.pick_sources(g, 3, seed=79):
+        print(f"[gpu] rmat18 src={s}", flush=True)
+        d, p, st = _run(g, int(s), gpu, parent=True)
+        ref = oracle.bfs(g, int(s))
+        assert np.array_equal(d, ref)
+        assert np.array_equal(p, oracle.parent(g, ref))
+
+
+def test_deterministic_repeats(gpu):
+    import torch
+    g = gg.rmat(16, 16, seed=5, perm_seed=6)
+    dg = pkg.DeviceGraph.from_csr(g, gpu)
+    plan = pkg.Plan([dg])
+    s = int(gg.pick_sources(g, 1, seed=7)[0])
+    outs = []
+    for _ in range(5):
+        d, p, _ = plan.run(0, s, parent=True)
+        torch.cuda.synchronize()
+        outs.append((d.cpu().numpy().tobytes(), p.cpu().numpy().tobytes()))
+    assert all(o == outs[0] for o in outs)
+    plan.close()
+
+
+def test_level_stats(gpu):
+    g = gg.rmat(14, 8, seed=3, perm_seed=4)
+    s = int(gg.pick_sources(g, 1, seed=5)[0])
+    ref = oracle.bfs(g, s)
+    deg = g.degrees()
+    for mode in (pkg.LOOP_PERSISTENT, pkg.LOOP_HOST):
+        dg = pkg.DeviceGraph.from_csr(g, gpu)
+        plan = pkg.Plan([dg], loop_mode=mode, collect_stats=True)
+        plan.run(0, s)
+        front, hist = plan.level_stats()
+        assert len(front) == ref.max() + 1
+        for L in range(len(front)):
+            lv = np.flatnonzero(ref == L)
+            assert front[L] == lv.size
+            bins = np.where(deg[lv] > 0, np.floor(np.log2(np.maximum(deg[lv], 1))).astype(int) + 1, 0)
+            assert np.array_equal(hist[L], np.bincount(bins, minlength=pkg.NUM_BINS)), L
+        plan.close()
+
+
+# ---------------------------------------------------------------------------
+# partitioned share: Phase 1 into the global bitmap, Phase 2 with staged
+# butterfly messages (one node of a 16-node 1D partition)
+# ---------------------------------------------------------------------------
+
+def _words_to_tensor(words, gpu):
+    import torch
+    return torch.from_numpy(words.view(np.int64).copy()).to(gpu)
+
+
+@pytest.mark.parametrize("scale,P,radix,node", [(14, 16, 2, 0), (14, 16, 4, 0), (13, 16, 2, 7),
+                                                (12, 4, 2, 3)])
+def test_partition_share_step_api(gpu, scale, P, radix, node):
+    import torch
+    g = gg.rmat(scale, 8, seed=100 + scale, perm_seed=200 + scale)
+    src = int(gg.pick_sources(g, 1, seed=300 + scale)[0])
+    ref = oracle.bfs(g, src)
+    b = gg.partition_1d(g.row_ptr, P)
+    local, inc = oracle.stage(g, ref, b, node, radix)
+    dg = pkg.DeviceGraph.from_csr(g, gpu, int(b[node]), int(b[node + 1]))
+    plan = pkg.Plan([dg])
+    dist = torch.empty(g.n, dtype=torch.int32, device=gpu)
+    plan.begin(0, src, dist)
+    W = (g.n + 63) // 64
+    L = 0
+    while True:
+        addr = plan.expand()
+        got_next = _read_device_words(addr, W, gpu)
+        expect = local[L] if L < local.shape[0] else np.zeros(W, dtype=np.uint64)
+        assert np.array_equal(got_next, expect), f"local next at level {L}"
+        msgs = [_words_to_tensor(inc[L, j], gpu) for j in range(inc.shape[1])] if L < local.shape[0] \
+            else [torch.zeros(W, dtype=torch.int64, device=gpu) for _ in range(inc.shape[1])]
+        gnew, onew = plan.merge_frontier(msgs)
+        exp_new = int((ref == L + 1).sum())
+        assert gnew == exp_new
+        own = (ref == L + 1)[b[node]:b[node + 1]].sum()
+        assert onew == own
+        if gnew == 0:
+            break
+        L += 1
+    st = plan.finish()
+    assert st.levels == L + 1 == ref.max() + 1
+    assert np.array_equal(dist.cpu().numpy(), ref)
+    assert st.edges_scanned == oracle.edges_scanned(g, ref, int(b[node]), int(b[node + 1]))
+    plan.close()
+
+
+def _read_device_words(addr, W, gpu):
+    """Copies W uint64 words at a raw device address to the host (hipMemcpy)."""
+    import torch
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    out = np.empty(W, dtype=np.uint64)
+    torch.cuda.synchronize()
+    assert hip.hipMemcpy(out.ctypes.data, addr, W * 8, 2) == 0  # DeviceToHost
+    return out
+
+
+@pytest.mark.parametrize("rounds", [False, True])
+def test_partition_share_run_with_exchange(gpu, rounds):
+    """bfs_run with an exchange callback serving the staged messages; with
+    `rounds` the messages are merged one butterfly round at a time."""
+    import torch
+    g = gg.rmat(15, 8, seed=400, perm_seed=401)
+    src = int(gg.pick_sources(g, 1, seed=402)[0])
+    ref = oracle.bfs(g, src)
+    b = gg.partition_1d(g.row_ptr, 16)
+    local, inc = oracle.stage(g, ref, b, 0, 2)
+    W = (g.n + 63) // 64
+    staged = [[_words_to_tensor(inc[L, j], gpu) for j in range(inc.shape[1])]
+              for L in range(local.shape[0])]
+    zeros = [torch.zeros(W, dtype=torch.int64, device=gpu) for _ in range(inc.shape[1])]
+    seen = []
+
+    def exchange(level, local_next):
+        seen.append(level)
+        got = _read_device_words(local_next, W, gpu)
+        exp = local[level] if level < local.shape[0] else np.zeros(W, dtype=np.uint64)
+        if not np.array_equal(got, exp):
+            raise AssertionError(level)
+        msgs = staged[level] if level < len(staged) else zeros
+        return [m.data_ptr() for m in msgs]
+
+    dg = pkg.DeviceGraph.from_csr(g, gpu, 0, int(b[1]))
+    if not rounds:
+        plan = pkg.Plan([dg], exchange=exchange)
+        d, _, st = plan.run(0, src)
+        assert np.array_equal(d.cpu().numpy(), ref)
+        assert seen == list(range(ref.max() + 1))
+        plan.close()
+    else:
+        plan = pkg.Plan([dg])
+        dist = torch.empty(g.n, dtype=torch.int32, device=gpu)
+        plan.begin(0, src, dist)
+        L = 0
+        while True:
+            plan.expand()
+            msgs = staged[L] if L < len(staged) else zeros
+            for j, m in enumerate(msgs):  # one round at a time, level kept open
+                plan.merge_frontier([m], keep_next=True)
+            gnew, _ = plan.merge_frontier([])
+            if gnew == 0:
+                break
+            L += 1
+        plan.finish()
+        assert np.array_equal(dist.cpu().numpy(), ref)
+        plan.close()
+
+
+# ---------------------------------------------------------------------------
+# merge kernel vs oracle merge on random bitmaps
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,k,vb,ve", [(1000, 0, 0, 1000), (70000, 3, 64, 40000),
+                                       (4097, 11, 1024, 4097), (130, 2, 64, 128),
+                                       (200000, 8, 0, 200000)])
+def test_merge_random_bitmaps(gpu, n, k, vb, ve):
+    import torch
+    rng = np.random.default_rng(n * 31 + k)
+    W = (n + 63) // 64
+    valid = np.zeros(W * 64, dtype=bool)
+    valid[:n] = True
+    vmask = np.packbits(valid, bitorder="little").view(np.uint64)
+    inc = [np.packbits(rng.random(W * 64) < 0.03, bitorder="little").view(np.uint64) & vmask
+           for _ in range(k)]
+    g = gg.empty_graph(n)
+    rp = np.zeros(ve - vb + 1, dtype=np.int64)
+    dg = pkg.DeviceGraph(n, vb, ve, torch.from_numpy(rp).to(gpu),
+                         torch.zeros(0, dtype=torch.int32, device=gpu))
+    plan = pkg.Plan([dg])
+    dist = torch.empty(n, dtype=torch.int32, device=gpu)
+    src = n // 3
+    plan.begin(0, src, dist)
+    plan.expand()
+    gnew, onew = plan.merge_frontier([_words_to_tensor(x, gpu) for x in inc])
+    # oracle on the same state: visited = {src}, next = empty
+    vis = np.zeros(W, dtype=np.uint64)
+    vis[src >> 6] = np.uint64(1) << np.uint64(src & 63)
+    odist = np.full(n, -1, dtype=np.int32)
+    odist[src] = 0
+    tot, q = oracle.merge(n, 0, np.zeros(W, dtype=np.uint64), inc, vis, odist, vb, ve)
+    assert gnew == tot and onew == q.size
+    assert np.array_equal(dist.cpu().numpy(), odist)
+    plan.close()
+    del g
+
+
+# ---------------------------------------------------------------------------
+# errors through the C ABI
+# ---------------------------------------------------------------------------
+
+def test_error_paths(gpu):
+    import torch
+    g = gg.rmat(10, 8, seed=1, perm_seed=2)
+    dg = pkg.DeviceGraph.from_csr(g, gpu)
+    plan = pkg.Plan([dg])
+    with pytest.raises(pkg.BfsError) as e:
+        plan.run(0, g.n)
+    assert e.value.status == 1
+    with pytest.raises(pkg.BfsError) as e:
+        plan.run(0, -1)
+    assert e.value.status == 1
+    with pytest.raises(pkg.BfsError) as e:
+        plan.run(1, 0)
+    assert e.value.status == 1
+    s = int(gg.pick_sources(g, 1, seed=3)[0])
+    d, _, _ = plan.run(0, s)  # still usable after errors
+    assert np.array_equal(d.cpu().numpy(), oracle.bfs(g, s))
+    plan.close()
+    # merge before begin
+    plan = pkg.Plan([dg])
+    with pytest.raises(pkg.BfsError) as e:
+        plan.merge_frontier([])
+    assert e.value.status == 7
+    plan.close()
+    # column id out of range is rejected at plan creation
+    bad = pkg.DeviceGraph(g.n, 0, g.n, dg.row_ptr, dg.col.clone())
+    bad.col[5] = g.n
+    with pytest.raises(pkg.BfsError) as e:
+        pkg.Plan([bad])
+    assert e.value.status == 1
+    # workspace too small
+    L = pkg.lib()
+    arr = (pkg.bfs_graph * 1)(dg.c_struct())
+    ws = torch.empty(1 << 12, dtype=torch.uint8, device=gpu)
+    h = ctypes.c_void_p(0)
+    st = L.bfs_plan_create(arr, 1, None, (ws.data_ptr() + 255) // 256 * 256, 1024, ctypes.byref(h))
+    assert st == 2
+    # exchange failure is reported and the plan stays usable
+    def failing(level, local_next):
+        raise RuntimeError("link down")
+    plan = pkg.Plan([dg], exchange=failing)
+    with pytest.raises(pkg.BfsError) as e:
+        plan.run(0, s)
+    assert e.value.status == 6
+    plan.close()
+
+
+@pytest.mark.parametrize("scale", [24])
+def test_full_size_rmat24_ef16(gpu, scale):
+    """The benchmark's workload (R-MAT scale 24, edge factor 16) in the
+    benchmark's launch configuration: full bit-exact distance arrays for two
+    seeded sources and the canonical parents of one."""
+    import torch
+    print("[gpu] generating rmat24", flush=True)
+    g = gg.rmat(scale, 16, seed=0x5EED0024, perm_seed=0xBEEF0024)
+    dg = pkg.DeviceGraph.from_csr(g, gpu)
+    plan = pkg.Plan([dg])
+    for i, s in enumerate(gg.pick_sources(g, 2, seed=0xC0FFEE24)):
+        print(f"[gpu] rmat24 src={s}", flush=True)
+        d, p, st = plan.run(0, int(s), parent=(i == 0))
+        torch.cuda.synchronize()
+        ref = oracle.bfs(g, int(s))
+        assert np.array_equal(d.cpu().numpy(), ref)
+        if i == 0:
+            assert np.array_equal(p.cpu().numpy(), oracle.parent(g, ref))
+        assert st.edges_scanned == oracle.edges_scanned(g, ref)
+    plan.close()
