@@ -104,7 +104,9 @@ typedef struct {
   int32_t levels;        /* number of nonempty levels = max distance + 1 */
   int64_t reached;       /* vertices with a finite distance (all n_global) */
   int64_t edges_scanned; /* sum of degrees of the owned frontier vertices */
-  float ms;              /* device time of the traversal (HIP events) */
+  float ms;              /* device time of the whole traversal, reset included (HIP events) */
+  float loop_ms;         /* device time of the level loop alone (the persistent launch, or
+                            first expansion to last merge when host-driven) */
 } bfs_stats;
 
 #define BFS_MAX_LEVEL_STATS 4096

@@ -47,7 +47,8 @@ class bfs_options(ctypes.Structure):
 
 class bfs_stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("reached", ctypes.c_int64),
-                ("edges_scanned", ctypes.c_int64), ("ms", ctypes.c_float)]
+                ("edges_scanned", ctypes.c_int64), ("ms", ctypes.c_float),
+                ("loop_ms", ctypes.c_float)]
 
 
 class bfs_query(ctypes.Structure):
@@ -151,6 +152,7 @@ class Stats:
     reached: int
     edges_scanned: int
     ms: float
+    loop_ms: float
 
 
 class Plan:
@@ -228,6 +230,9 @@ class Plan:
     def run(self, graph: int, source: int, dist=None, parent: bool = False):
         """Single-source traversal. Returns (dist, parent or None, Stats)."""
         torch = _torch()
+        if not 0 <= graph < len(self.graphs):
+            # let the C ABI report the bad index
+            self._check(lib().bfs_run(self.h, graph, int(source), None, None, None))
         g = self.graphs[graph]
         dev = g.row_ptr.device
         if dist is None:
@@ -236,7 +241,7 @@ class Plan:
         st = bfs_stats()
         self._check(lib().bfs_run(self.h, graph, int(source), dist.data_ptr(),
                                   par.data_ptr() if par is not None else None, ctypes.byref(st)))
-        return dist, par, Stats(st.levels, st.reached, st.edges_scanned, st.ms)
+        return dist, par, Stats(st.levels, st.reached, st.edges_scanned, st.ms, st.loop_ms)
 
     def begin(self, graph: int, source: int, dist):
         self._check(lib().bfs_begin(self.h, graph, int(source), dist.data_ptr()))
@@ -262,7 +267,7 @@ class Plan:
         st = bfs_stats()
         self._check(lib().bfs_finish(self.h, parent.data_ptr() if parent is not None else None,
                                      ctypes.byref(st)))
-        return Stats(st.levels, st.reached, st.edges_scanned, st.ms)
+        return Stats(st.levels, st.reached, st.edges_scanned, st.ms, st.loop_ms)
 
     def level_stats(self):
         """(frontier sizes per level, degree-bin histogram [levels, 34])."""

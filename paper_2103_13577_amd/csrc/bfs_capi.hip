@@ -295,6 +295,7 @@ bfs_status bfs_finish(bfs_plan_t p, int32_t *parent, bfs_stats *st) {
     st->reached = (int64_t)c.reached;
     st->edges_scanned = (int64_t)c.edges;
     st->ms = p->last_ms;
+    st->loop_ms = p->last_loop_ms;
   }
   return BFS_OK;
 }
@@ -307,6 +308,7 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   hipEvent_t ev0 = p->ev[0], ev1 = p->ev[1];
   p->persistent_levels = 0;
   p->last_ms = 0.f;
+  p->last_loop_ms = 0.f;
   e = hipEventRecord(ev0, p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
   s = bfs_begin(p, graph, source, dist);
@@ -319,6 +321,8 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   if (!host_loop) {
     View v = p->view(graph, dist);
     const int max_levels = (int)std::min<int64_t>(g.n_global + 1, 1ll << 30);
+    e = hipEventRecord(p->ev[2], p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
     e = launch_persistent(v, max_levels, p->persist_grid, p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "persistent launch");
     e = hipEventRecord(ev1, p->stream);
@@ -331,6 +335,8 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
     p->persistent_levels = c.levels;
     p->level = c.levels;
   } else {
+    e = hipEventRecord(p->ev[2], p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
     for (;;) {
       const uint64_t *local_next = nullptr;
       s = bfs_expand(p, &local_next);
@@ -354,9 +360,11 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   }
   e = hipEventSynchronize(ev1);
   if (e != hipSuccess) return p->hip_fail(e, "hipEventSynchronize");
-  float ms = 0.f;
+  float ms = 0.f, lms = 0.f;
   if (hipEventElapsedTime(&ms, ev0, ev1) != hipSuccess) ms = -1.f;
+  if (hipEventElapsedTime(&lms, p->ev[2], ev1) != hipSuccess) lms = -1.f;
   p->last_ms = ms;
+  p->last_loop_ms = lms;
   return bfs_finish(p, parent, st);
 }
 

@@ -407,7 +407,6 @@ __global__ void k_clear_stats_row(View v, int level) {
 // until a level finds no new vertex. Every block runs the same number of
 // barriers; the loop also stops if a barrier tripped its spin limit.
 __global__ void __launch_bounds__(kBlock) k_persistent(View v, int max_levels) {
-  uint32_t gen = 0;
   const uint32_t nb = gridDim.x;
   MergeArgs a;
   a.k = 0;
@@ -420,10 +419,10 @@ __global__ void __launch_bounds__(kBlock) k_persistent(View v, int max_levels) {
           v.lvl_hist[(L + 1) * kNumBins + b] = 0;
     }
     expand_phase(v, L, blockIdx.x, nb);
-    grid_barrier(&v.ctl->bar, nb, gen);
+    grid_barrier(&v.ctl->bar, nb);
     a.level = L;
     merge_phase(v, a, blockIdx.x, nb);
-    grid_barrier(&v.ctl->bar, nb, gen);
+    grid_barrier(&v.ctl->bar, nb);
     const uint64_t nn = load_relaxed64(&v.ctl->newcnt[L % 3]);
     if (v.stats && blockIdx.x == 0 && threadIdx.x == 0 && L + 1 < kMaxStatLevels)
       v.lvl_frontier[L + 1] = (int64_t)load_relaxed64(&v.ctl->ownedcnt[L % 3]);

@@ -79,8 +79,8 @@ __device__ __forceinline__ int32_t load_relaxed_i32(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier state. `count` and `gen` start at 0 before a cooperative launch
-// (the reset kernel clears them); every block keeps its own generation.
+// Grid barrier state, valid from any initial generation value; `count` must be
+// 0 when no block is inside a barrier (the last arriver resets it).
 struct GridBarrier {
   uint32_t count;
   uint32_t gen;
@@ -88,28 +88,31 @@ struct GridBarrier {
   uint32_t pad;
 };
 
-// Spin limit per barrier wait: ~2^22 sleeps of 64 clocks is ~0.1 s at 2.4 GHz,
-// orders of magnitude above any legitimate wait for co-resident blocks.
+// Spin limit per barrier wait: ~2^22 sleeps of 64 clocks plus the polling
+// loads is well over 0.1 s, orders of magnitude above any legitimate wait
+// for co-resident blocks.
 constexpr uint32_t kSpinLimit = 1u << 22;
 
 // All blocks of a cooperative launch must call this the same number of times.
-// Release/acquire at agent scope make every write before the barrier visible
-// to every read after it. If a wait exceeds the spin limit the barrier marks
-// `tripped` and lets the block continue, so the kernel always terminates; the
-// host reports the trip as an error.
-__device__ __forceinline__ void grid_barrier(GridBarrier *b, uint32_t nblocks, uint32_t &gen) {
+// Each block reads the generation before it arrives (the generation cannot
+// move until every block has arrived); the last arriver resets the count and
+// advances the generation. Release/acquire at agent scope make every write
+// before the barrier visible to every read after it. If a wait exceeds the
+// spin limit the barrier marks `tripped` and lets the block continue, so the
+// kernel always terminates; the host reports the trip as an error.
+__device__ __forceinline__ void grid_barrier(GridBarrier *b, uint32_t nblocks) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t target = gen + 1;
+    const uint32_t g0 = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    uint32_t arrived =
+    const uint32_t arrived =
         __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
     if (arrived == nblocks) {
       __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&b->gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       uint32_t spins = 0;
-      while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
+      while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
         __builtin_amdgcn_s_sleep(1);
         if (++spins > kSpinLimit) {
           __hip_atomic_store(&b->tripped, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -119,7 +122,6 @@ __device__ __forceinline__ void grid_barrier(GridBarrier *b, uint32_t nblocks, u
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
-  gen += 1;
   __syncthreads();
 }
 

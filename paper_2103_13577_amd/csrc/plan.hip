@@ -74,8 +74,13 @@ bfs_status choose_tuning(Plan *p) {
     const int64_t m = p->graphs[i].m;
     if ((m >> t.chunk_shift) + (p->graphs[i].v_end - p->graphs[i].v_begin) >= (1ll << 32))
       return p->fail(BFS_ERR_ARG, "chunk_edges too small for this graph");
-    if (p->graphs[i].v_end - p->graphs[i].v_begin >= (1ll << (64 - kHeavyShift)))
-      return p->fail(BFS_ERR_ARG, "owned range too large");
+    // The workgroup-tier queue length shares a 64-bit counter with the chunk
+    // total: it must stay below 2^(64-40). Its vertices have degree at least
+    // 2^(wave_bin-1), so there are at most m / 2^(wave_bin-1) of them.
+    const int64_t heavy_max = std::min<int64_t>(p->graphs[i].v_end - p->graphs[i].v_begin,
+                                                (m >> (t.wave_bin - 1)) + 1);
+    if (heavy_max >= (1ll << (64 - kHeavyShift)))
+      return p->fail(BFS_ERR_ARG, "wave_bin too small for this graph (workgroup-tier queue overflow)");
   }
   return BFS_OK;
 }

@@ -24,11 +24,13 @@ struct WsLayout {
   size_t ctl, lvl_frontier, lvl_hist, visited, next;
   size_t q[3][2];
   size_t cstart[2];
-  // batched multi-source state (per graph)
-  std::vector<size_t> ms_front, ms_next, ms_seen;  // uint64[n_g * lanes] each
-  std::vector<size_t> ms_queue[2];                 // int32[n_g] active-vertex queues
-  size_t ms_ctl = 0;                               // per-graph control blocks
-  size_t ms_dirty = 0;
+  // batched multi-source state (see msbfs_core.hpp)
+  bool ms_on = false;
+  int64_t ms_ntot = 0, ms_mtot = 0;
+  size_t ms_ctl, ms_graphs, ms_rp, ms_col, ms_F, ms_N, ms_S;
+  size_t ms_q[3][2], ms_cstart[2], ms_extra;
+  size_t ms_slot_out, ms_slot_type, ms_slot_start, ms_slot_active, ms_newmask, ms_depth_err;
+  size_t ms_admit, ms_mask;
 };
 
 // Tier thresholds per graph (degree bins; see bfs_core.hpp).
@@ -53,7 +55,7 @@ struct bfs_plan_s {
   int num_cus = 0;
   int coop = 0;
   int persist_grid = 0;
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::string err;
 
   // single-source traversal state
@@ -66,6 +68,7 @@ struct bfs_plan_s {
   int32_t persistent_levels = 0;
   int64_t last_level_new = 0;
   float last_ms = 0.f;
+  float last_loop_ms = 0.f;
   std::vector<int64_t> level_frontier;
 
   bfsk::BatchState *batch = nullptr;

@@ -1,0 +1,171 @@
+"""GPU parity of the batched multi-source path and of the serving loop.
+
+Every query's distances must equal the oracle's for its (graph, source),
+bit for bit (uint8 with 255 = unreached, or int32 with -1), whether the query
+ran alone, in a one-launch batch, or joined a running batch.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_2103_13577_amd as pkg
+
+pytestmark = pytest.mark.gpu
+
+
+def _graphs_small():
+    return [gg.rmat(s, 8, seed=900 + s, perm_seed=950 + s) for s in (9, 10, 11, 12)] + \
+           [gg.grid(40, 30, 0.02, seed=5), gg.path_graph(200), gg.star_graph(300),
+            gg.disjoint_union(gg.cycle_graph(50), gg.complete_graph(20))]
+
+
+def _oracle_out(g, s, dtype):
+    d = oracle.bfs(g, int(s))
+    if dtype == "u8":
+        return np.where(d < 0, 255, d).astype(np.uint8)
+    return d
+
+
+@pytest.mark.parametrize("lw", [1, 2, 4])
+def test_one_launch_batch_u8(gpu, lw):
+    import torch
+    gs = _graphs_small()
+    dgs = [pkg.DeviceGraph.from_csr(g, gpu) for g in gs]
+    plan = pkg.Plan(dgs, batch_lanes=lw)
+    qs, refs = [], []
+    for gi, g in enumerate(gs):
+        srcs = gg.pick_sources(g, min(64 * lw, 40 + 7 * gi), seed=1000 + gi)
+        srcs[:3] = srcs[0]  # duplicate sources share a batch
+        for s in srcs:
+            out = torch.empty(g.n, dtype=torch.uint8, device=gpu)
+            qs.append((gi, int(s), out))
+            refs.append(_oracle_out(g, s, "u8"))
+    print(f"[gpu] batch lw={lw} queries={len(qs)}", flush=True)
+    t = plan.batch_submit(qs, pkg.BATCH_ONE_LAUNCH)
+    r = plan.batch_wait(t)
+    assert r.status == 0 and r.nq == len(qs)
+    for (gi, s, out), ref in zip(qs, refs):
+        assert np.array_equal(out.cpu().numpy(), ref), (gi, s)
+    plan.close()
+
+
+def test_more_queries_than_slots_int32(gpu):
+    """300 queries on one graph with 64 slots: admission waits for free slots,
+    released slots are cleared and reused, every answer is exact."""
+    import torch
+    g = gg.rmat(11, 8, seed=31, perm_seed=32)
+    plan = pkg.Plan([pkg.DeviceGraph.from_csr(g, gpu)], batch_lanes=1)
+    srcs = gg.pick_sources(g, 300, seed=33)
+    outs = [torch.empty(g.n, dtype=torch.int32, device=gpu) for _ in srcs]
+    t = plan.batch_submit([(0, int(s), o) for s, o in zip(srcs, outs)], pkg.BATCH_ONE_LAUNCH)
+    plan.batch_wait(t)
+    for s, o in zip(srcs, outs):
+        assert np.array_equal(o.cpu().numpy(), oracle.bfs(g, int(s))), int(s)
+    plan.close()
+
+
+def test_depth_overflow_u8_and_int32_ok(gpu):
+    import torch
+    g = gg.path_graph(300)
+    plan = pkg.Plan([pkg.DeviceGraph.from_csr(g, gpu)], batch_lanes=1)
+    o8 = torch.empty(g.n, dtype=torch.uint8, device=gpu)
+    t = plan.batch_submit([(0, 0, o8)])
+    with pytest.raises(pkg.BfsError) as e:
+        plan.batch_wait(t)
+    assert e.value.status == 4
+    o32 = torch.empty(g.n, dtype=torch.int32, device=gpu)
+    t = plan.batch_submit([(0, 0, o32), (0, 299, torch.empty(g.n, dtype=torch.uint8, device=gpu))])
+    with pytest.raises(pkg.BfsError):
+        plan.batch_wait(t)  # the uint8 query overflows; the int32 one is exact
+    assert np.array_equal(o32.cpu().numpy(), oracle.bfs(g, 0))
+    t = plan.batch_submit([(0, 150, o8)])  # depth 150 fits
+    plan.batch_wait(t)
+    assert np.array_equal(o8.cpu().numpy(), _oracle_out(g, 150, "u8"))
+    plan.close()
+
+
+def test_streaming_alone_equals_in_mix(gpu):
+    """Queries submitted while others are running (continuous batching) give
+    the same answer as the same query run alone through bfs_run."""
+    import torch
+    gs = [gg.rmat(13, 8, seed=41, perm_seed=42), gg.grid(64, 64, 0.01, seed=43),
+          gg.lollipop_graph(64, 300)]
+    dgs = [pkg.DeviceGraph.from_csr(g, gpu) for g in gs]
+    plan = pkg.Plan(dgs, batch_lanes=1)
+    alone = pkg.Plan(dgs)
+    rng = np.random.default_rng(7)
+    tickets, items = [], []
+    for wave in range(6):
+        batch = []
+        for _ in range(25):
+            gi = int(rng.integers(0, len(gs)))
+            s = int(gg.pick_sources(gs[gi], 1, seed=int(rng.integers(1 << 30)))[0])
+            out = torch.empty(gs[gi].n, dtype=torch.int32, device=gpu)
+            batch.append((gi, s, out))
+        tickets.append((plan.batch_submit(batch, pkg.BATCH_STREAMING), len(batch)))
+        items += batch
+        time.sleep(0.002)
+    for t, nq in tickets:
+        plan.batch_wait(t)
+        times = plan.batch_times(t, nq)
+        assert np.all(times > 0)
+    for gi, s, out in items:
+        d, _, _ = alone.run(gi, s)
+        assert np.array_equal(out.cpu().numpy(), d.cpu().numpy()), (gi, s)
+        assert np.array_equal(out.cpu().numpy(), oracle.bfs(gs[gi], s)), (gi, s)
+    plan.close()
+    alone.close()
+
+
+def test_batch_errors(gpu):
+    import torch
+    g = gg.rmat(9, 8, seed=1, perm_seed=2)
+    dg = pkg.DeviceGraph.from_csr(g, gpu)
+    plain = pkg.Plan([dg])
+    out = torch.empty(g.n, dtype=torch.uint8, device=gpu)
+    with pytest.raises(pkg.BfsError) as e:
+        plain.batch_submit([(0, 0, out)])
+    assert e.value.status == 5
+    plain.close()
+    plan = pkg.Plan([dg], batch_lanes=1)
+    with pytest.raises(pkg.BfsError) as e:
+        plan.batch_submit([(0, g.n, out)])
+    assert e.value.status == 1
+    with pytest.raises(pkg.BfsError) as e:
+        plan.batch_submit([(3, 0, out)])
+    assert e.value.status == 1
+    s = int(gg.pick_sources(g, 1, seed=3)[0])
+    t = plan.batch_submit([(0, s, out)])
+    plan.batch_wait(t)
+    assert np.array_equal(out.cpu().numpy(), _oracle_out(g, s, "u8"))
+    plan.close()
+
+
+def test_full_size_batch_config(gpu):
+    """1024 sources over R-MAT scales 16,17,18,19,20,21,22,22 (edge factor 16)
+    in one launch, uint8 outputs: every output equals the single-source GPU
+    path (bit-exact), and two sources per graph equal the CPU oracle."""
+    import torch
+    scales = [16, 17, 18, 19, 20, 21, 22, 22]
+    gs = [gg.rmat(s, 16, seed=0x5EED0400 + i, perm_seed=0xBEEF0400 + i) for i, s in enumerate(scales)]
+    dgs = [pkg.DeviceGraph.from_csr(g, gpu) for g in gs]
+    plan = pkg.Plan(dgs, batch_lanes=2)
+    qs = []
+    for gi, g in enumerate(gs):
+        for s in gg.pick_sources(g, 128, seed=0xC0FFEE00 + gi):
+            qs.append((gi, int(s), torch.empty(g.n, dtype=torch.uint8, device=gpu)))
+    print("[gpu] full batch submit", flush=True)
+    t = plan.batch_submit(qs, pkg.BATCH_ONE_LAUNCH)
+    plan.batch_wait(t)
+    single = pkg.Plan(dgs)
+    for i, (gi, s, out) in enumerate(qs):
+        d, _, _ = single.run(gi, s)
+        ref = torch.where(d < 0, torch.full_like(d, 255), d).to(torch.uint8)
+        assert torch.equal(out, ref), (gi, s)
+        if i % 128 < 2:
+            assert np.array_equal(out.cpu().numpy(), _oracle_out(gs[gi], s, "u8")), (gi, s)
+    single.close()
+    plan.close()
