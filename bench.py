@@ -161,6 +161,363 @@ def run_single(args, name, scale, ef):
     return out
 
 
+# ---------------------------------------------------------------------------
+# batched multi-source workload: 1024 sources over 8 R-MAT graphs
+# ---------------------------------------------------------------------------
+
+BATCH_SCALES = [16, 17, 18, 19, 20, 21, 22, 22]
+
+
+def run_batch(args):
+    """1024 sources (128 per graph) over R-MAT scales 16..22,22 (edge factor
+    16) as one bitset multi-source launch with uint8 outputs, against the same
+    1024 (graph, source) pairs run one at a time through bfs_run."""
+    import torch
+    import paper_2103_13577_amd as pkg
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    gs = [gg.rmat(s, 16, seed=0x5EED0400 + i, perm_seed=0xBEEF0400 + i)
+          for i, s in enumerate(BATCH_SCALES)]
+    log(f"generated batch graphs in {time.time() - t0:.1f}s")
+    dgs = [pkg.DeviceGraph.from_csr(g, dev) for g in gs]
+    plan = pkg.Plan(dgs, batch_lanes=2, grid_blocks=args.grid_blocks)
+    single = pkg.Plan(dgs, grid_blocks=args.grid_blocks)
+    qs = []
+    for gi, g in enumerate(gs):
+        for s in gg.pick_sources(g, 128, seed=0xC0FFEE00 + gi):
+            qs.append((gi, int(s), torch.empty(g.n, dtype=torch.uint8, device=dev)))
+    # warm-up
+    for _ in range(max(args.warmup, 1)):
+        plan.batch_wait(plan.batch_submit(qs, pkg.BATCH_ONE_LAUNCH))
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 8))
+    times = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        tk = plan.batch_submit(qs, pkg.BATCH_ONE_LAUNCH)
+        plan.batch_wait(tk)
+        times.append(time.perf_counter() - t)
+    t_batch = float(np.median(times))
+    # one query at a time, same pairs
+    dist = torch.empty(max(g.n for g in gs), dtype=torch.int32, device=dev)
+    exact = True
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for gi, s, _ in qs:
+        single.run(gi, s, dist=dist[:gs[gi].n])
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t
+    for gi, s, out in qs:
+        d, _, _ = single.run(gi, s)
+        ref = torch.where(d < 0, torch.full_like(d, 255), d).to(torch.uint8)
+        if not torch.equal(out, ref):
+            exact = False
+    out = {
+        "metric": "batched queries/sec (1024 sources, 8 R-MAT graphs, one launch)",
+        "value": round(len(qs) / t_batch, 1), "unit": "queries/s", "n_gpus": 1,
+        "steps": reps, "warmup": max(args.warmup, 1), "ms_per_step": round(t_batch * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "batched multi-source BFS, 1024 sources over R-MAT scales "
+                               "16,17,18,19,20,21,22,22 (edge factor 16), 128 per graph, "
+                               "64 sources per uint64 lane word, uint8 distances",
+                   "lanes_per_graph": 2},
+        "plain_one_at_a_time": {"value": round(len(qs) / t_plain, 1), "unit": "queries/s",
+                                "seconds": round(t_plain, 4)},
+        "speedup_vs_plain": round(t_plain / t_batch, 2),
+        "latency_ms": {"p50": round(t_batch * 1e3, 3), "p99": round(t_batch * 1e3, 3),
+                       "note": "one launch: every query completes with the batch"},
+        "exact_vs_plain": exact,
+    }
+    plan.close()
+    single.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# serving workload: Poisson stream over a resident pool
+# ---------------------------------------------------------------------------
+
+def _serve_pool():
+    return [
+        ("rmat18", lambda: gg.rmat(18, 16, seed=0x5EED0518, perm_seed=0xBEEF0518)),
+        ("rmat22", lambda: gg.rmat(22, 16, seed=0x5EED0522, perm_seed=0xBEEF0522)),
+        ("rmat26", lambda: gg.rmat(26, 16, seed=0x5EED0526, perm_seed=0xBEEF0526)),
+        ("grid4096x4096", lambda: gg.grid(4096, 4096, 0.01, seed=0x5EED0540)),
+        ("grid16384x1024", lambda: gg.grid(16384, 1024, 0.01, seed=0x5EED0541)),
+    ]
+
+
+def run_serve(args):
+    """Open-loop Poisson stream (mean 20k queries/s, 10k queries) of
+    single-source queries over a resident pool; continuous batching in the
+    library's serving loop against FIFO one-at-a-time bfs_run."""
+    import threading
+    import torch
+    import paper_2103_13577_amd as pkg
+    dev = torch.device("cuda:0")
+    nq = args.serve_queries
+    t0 = time.time()
+    names, gs = [], []
+    for name, make in _serve_pool():
+        g = make()
+        names.append(name)
+        gs.append(g)
+        log(f"generated {name}: n={g.n} m={g.m} ({time.time() - t0:.0f}s)")
+    dgs = [pkg.DeviceGraph.from_csr(g, dev) for g in gs]
+    plan = pkg.Plan(dgs, batch_lanes=args.serve_lanes, grid_blocks=args.grid_blocks)
+    single = pkg.Plan(dgs, grid_blocks=args.grid_blocks)
+    arrivals = gg.poisson_arrivals(nq, 20000.0, seed=0x5EED0550)
+    gsel = (gg.draws(0x5EED0551, nq) % np.uint64(len(gs))).astype(np.int64)
+    srcs = np.zeros(nq, dtype=np.int64)
+    for gi in range(len(gs)):
+        idx = np.flatnonzero(gsel == gi)
+        srcs[idx] = gg.pick_sources(gs[gi], idx.size, seed=0x5EED0560 + gi)
+    # output buffers: a pool per graph bounds the memory held by queries in
+    # flight or waiting; a query takes a buffer at its arrival (waiting for one
+    # if none is free: that wait counts in its latency)
+    per_graph = args.serve_buffers
+    pools = [[torch.empty(g.n, dtype=torch.int32, device=dev) for _ in range(per_graph)] for g in gs]
+    free = [list(range(per_graph)) for _ in gs]
+    cv = threading.Condition()
+    hash_w = {g.n: None for g in gs}
+    for n in hash_w:
+        hash_w[n] = torch.from_numpy(
+            (gg.draws(0x5EED0570 + n, n) >> np.uint64(40)).astype(np.int64)).to(dev)
+    hstream = torch.cuda.Stream()
+
+    def out_hash(t):
+        with torch.cuda.stream(hstream):
+            return int(((t.to(torch.int64) + 2) * hash_w[t.numel()]).sum().item())
+
+    hashes = [None] * nq
+    done_t = np.zeros(nq)
+    tickets = {}
+    start = [None]
+    lock_err = []
+
+    def consumer():
+        pending = set()
+        while True:
+            with cv:
+                while not tickets and len(pending) == 0 and not (start[0] == "done"):
+                    cv.wait(0.01)
+                for k, v in list(tickets.items()):
+                    pending.add(k)
+                    del tickets[k]
+                if not pending and start[0] == "done":
+                    return
+            for i in list(pending):
+                tk, gi, bi = i
+                try:
+                    r = plan.batch_wait(tk, timeout_us=0)
+                except pkg.BfsError as e:
+                    if e.status == 8:
+                        continue
+                    lock_err.append(str(e))
+                    pending.discard(i)
+                    continue
+                q = tk_query[tk]
+                done_t[q] = r.complete_ns * 1e-9
+                hashes[q] = out_hash(pools[gi][bi])
+                pending.discard(i)
+                with cv:
+                    free[gi].append(bi)
+                    cv.notify_all()
+            time.sleep(0.0002)
+
+    tk_query = {}
+    th = threading.Thread(target=consumer, daemon=True)
+    th.start()
+    t_start = time.perf_counter()
+    t_start_mono = time.monotonic()
+    for q in range(nq):
+        target = t_start + arrivals[q]
+        delay = target - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        gi = int(gsel[q])
+        with cv:
+            while not free[gi]:
+                cv.wait()
+            bi = free[gi].pop()
+        tk = plan.batch_submit([(gi, int(srcs[q]), pools[gi][bi])], pkg.BATCH_STREAMING)
+        tk_query[tk] = q
+        with cv:
+            tickets[(tk, gi, bi)] = True
+            cv.notify_all()
+    with cv:
+        start[0] = "done"
+        cv.notify_all()
+    th.join()
+    t_end = max(done_t)
+    arr_abs = t_start_mono + arrivals  # steady-clock time of each arrival
+    lat = done_t - arr_abs
+    served_qps = nq / (t_end - arr_abs[0])
+    # sequential plain baseline on a seeded sample of the same trace
+    samp = np.sort(gg.draws(0x5EED0580, min(args.serve_sample, nq)) % np.uint64(nq)).astype(np.int64)
+    samp = np.unique(samp)
+    exact = 0
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    svc = []
+    for q in samp:
+        gi = int(gsel[q])
+        ts = time.perf_counter()
+        d, _, _ = single.run(gi, int(srcs[q]), dist=pools[gi][0])
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - ts)
+        if out_hash(d) == hashes[q]:
+            exact += 1
+    t_plain = time.perf_counter() - t
+    plain_qps = samp.size / t_plain
+    # FIFO one-at-a-time service of the whole trace, with each query's service
+    # time drawn from the measured sample of its graph
+    by_g = {gi: [s for s, q in zip(svc, samp) if gsel[q] == gi] for gi in range(len(gs))}
+    clock, plain_lat = 0.0, []
+    for q in range(nq):
+        st = by_g[int(gsel[q])]
+        service = float(np.mean(st)) if st else float(np.mean(svc))
+        clock = max(clock, arrivals[q]) + service
+        plain_lat.append(clock - arrivals[q])
+    per_graph_lat = {names[gi]: {"p50_ms": round(metrics.percentile(lat[gsel == gi], 50) * 1e3, 2),
+                                 "p99_ms": round(metrics.percentile(lat[gsel == gi], 99) * 1e3, 2),
+                                 "n": int((gsel == gi).sum())} for gi in range(len(gs))}
+    out = {
+        "metric": "served queries/sec with p50/p99 latency (Poisson stream, resident pool)",
+        "value": round(served_qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": nq,
+        "warmup": 0, "ms_per_step": round(1e3 / served_qps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "serving: Poisson arrivals, mean 20k queries/s, "
+                               f"{nq} queries, uniform over R-MAT 18/22/26 (ef 16) and grids "
+                               "4096x4096, 16384x1024 with 1% edge deletions",
+                   "lanes_per_graph": args.serve_lanes, "buffers_per_graph": per_graph},
+        "latency_ms": {"p50": round(metrics.percentile(lat, 50) * 1e3, 2),
+                       "p99": round(metrics.percentile(lat, 99) * 1e3, 2)},
+        "per_graph": per_graph_lat,
+        "plain_fifo": {"qps": round(plain_qps, 1),
+                       "p50_ms": round(metrics.percentile(plain_lat, 50) * 1e3, 2),
+                       "p99_ms": round(metrics.percentile(plain_lat, 99) * 1e3, 2),
+                       "sample": int(samp.size)},
+        "speedup_qps_vs_plain": round(served_qps / plain_qps, 2),
+        "exact_sample": f"{exact}/{samp.size} served answers equal to bfs_run (64-bit hash)",
+        "errors": lock_err[:3],
+    }
+    plan.close()
+    single.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# one node's share of R-MAT scale 29 with staged butterfly messages
+# ---------------------------------------------------------------------------
+
+def run_share29(args):
+    """Partition 0 of a 16-way 1D partition of R-MAT scale 29, edge factor 8:
+    only partition 0's rows are resident; the frontier bitmaps span all 2^29
+    vertices. Each level runs the local expansion, then merges the 4
+    butterfly-stage bitmaps (fanout one, 16 nodes) computed by the oracle from
+    the full traversal and staged in device memory."""
+    import torch
+    import oracle
+    import paper_2103_13577_amd as pkg
+    dev = torch.device("cuda:0")
+    scale, P = args.share_scale, 16
+    t0 = time.time()
+    g = gg.rmat(scale, 8, seed=0x5EED0029, perm_seed=0xBEEF0029)
+    log(f"generated rmat{scale}: n={g.n} m={g.m} in {time.time() - t0:.0f}s")
+    b = gg.partition_1d(g.row_ptr, P)
+    src = int(gg.pick_sources(g, 1, seed=0xC0FFEE29)[0])
+    t0 = time.perf_counter()
+    ref = oracle.bfs(g, src)
+    t_oracle = time.perf_counter() - t0
+    m_all = oracle.edges_scanned(g, ref)
+    log(f"oracle full traversal {t_oracle:.1f}s levels={ref.max() + 1}")
+    local, inc = oracle.stage(g, ref, b, 0, 2)
+    log(f"staged {local.shape[0]} levels x {inc.shape[1]} messages")
+    W = (g.n + 63) // 64
+    dg = pkg.DeviceGraph.from_csr(g, dev, 0, int(b[1]))
+    staged = [[torch.from_numpy(inc[L, j].view(np.int64)).to(dev) for j in range(inc.shape[1])]
+              for L in range(local.shape[0])]
+    zeros = [torch.zeros(W, dtype=torch.int64, device=dev) for _ in range(inc.shape[1])]
+    local_ref = local
+    del inc
+    plan = pkg.Plan([dg])
+    dist = torch.empty(g.n, dtype=torch.int32, device=dev)
+    e_share = oracle.edges_scanned(g, ref, 0, int(b[1]))
+
+    def one(check):
+        ev = []
+        t_begin = torch.cuda.Event(enable_timing=True)
+        t_begin.record()
+        plan.begin(0, src, dist)
+        L = 0
+        ok = True
+        while True:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e2 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            addr = plan.expand()
+            e1.record()
+            if check:
+                torch.cuda.synchronize()
+                got = torch.empty(W, dtype=torch.int64, device=dev)
+                import ctypes
+                hip = ctypes.CDLL("libamdhip64.so")
+                hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+                hip.hipMemcpy(got.data_ptr(), addr, W * 8, 3)
+                exp = local_ref[L] if L < local_ref.shape[0] else np.zeros(W, dtype=np.uint64)
+                ok &= bool(np.array_equal(got.cpu().numpy().view(np.uint64), exp))
+            msgs = staged[L] if L < len(staged) else zeros
+            gnew, _ = plan.merge_frontier(msgs)
+            e2.record()
+            ev.append((e0, e1, e2))
+            if gnew == 0:
+                break
+            L += 1
+        st = plan.finish()
+        torch.cuda.synchronize()
+        exp_ms = [a.elapsed_time(bb) for a, bb, c in ev]
+        mrg_ms = [bb.elapsed_time(c) for a, bb, c in ev]
+        total = t_begin.elapsed_time(ev[-1][2])
+        return st, exp_ms, mrg_ms, total, ok
+
+    st, _, _, _, ok = one(check=True)
+    exact = ok and np.array_equal(dist.cpu().numpy(), ref)
+    runs = [one(check=False) for _ in range(max(args.steps if args.steps < 64 else 3, 1))]
+    tot = np.array([r[3] for r in runs])
+    exp_ms = np.mean([r[1] for r in runs], axis=0)
+    mrg_ms = np.mean([r[2] for r in runs], axis=0)
+    k = 4
+    merge_bytes = (k + 3) * W * 8
+    mrg_gbs = merge_bytes / (np.mean(mrg_ms) * 1e-3) / 1e9
+    out = {
+        "metric": "GTEPS over the share's scanned edges (one node of 16, staged butterfly messages)",
+        "value": round(metrics.gteps(e_share, float(np.median(tot)) * 1e-3), 3), "unit": "GTEPS",
+        "n_gpus": 1, "steps": len(runs), "warmup": 1, "ms_per_step": round(float(np.median(tot)), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"partition 0 of 16 of R-MAT scale {scale} edge factor 8, int32 CSR "
+                               "share, 2^29-bit frontier bitmaps, 4 staged butterfly-stage bitmaps "
+                               "per level (fanout one)",
+                   "n": g.n, "m_directed": g.m, "share_rows": int(b[1]),
+                   "share_edges": int(g.row_ptr[b[1]]), "levels": int(st.levels)},
+        "per_level_ms": {"expand": [round(x, 3) for x in exp_ms], "merge": [round(x, 3) for x in mrg_ms]},
+        "roofline": {"bound": "hbm", "kernel": "k_merge", "achieved": round(mrg_gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(mrg_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": int(merge_bytes)},
+        "exact": bool(exact),
+        "cpu_baseline": {"value": round(metrics.gteps(m_all, t_oracle), 4), "unit": "GTEPS",
+                         "cores": 1, "kind": "oracle",
+                         "sample": "the oracle's full traversal of the whole scale-29 graph "
+                                   f"from the same source ({t_oracle:.0f} s)"},
+        "edges_scanned_share": int(e_share),
+    }
+    plan.close()
+    return out
+
+
 def copy_probe(nbytes):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -187,6 +544,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=int, default=0)
+    ap.add_argument("--serve-queries", type=int, default=10000)
+    ap.add_argument("--serve-lanes", type=int, default=1)
+    ap.add_argument("--serve-buffers", type=int, default=96)
+    ap.add_argument("--serve-sample", type=int, default=200)
+    ap.add_argument("--share-scale", type=int, default=29)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
@@ -200,9 +562,12 @@ def main():
         out = run_single(args, "rmat24", 24, 16)
     elif args.workload == "rmat14":
         out = run_single(args, "rmat14", 14, 8)
+    elif args.workload == "batch":
+        out = run_batch(args)
+    elif args.workload == "serve":
+        out = run_serve(args)
     else:
-        from paper_2103_13577_amd import workloads
-        out = workloads.run(args)
+        out = run_share29(args)
     print(json.dumps(out), flush=True)
 
 

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -21,6 +22,14 @@
 #include <vector>
 
 namespace {
+
+// One line on stderr per construction phase for very large graphs.
+void phase(int64_t n, const char *what) {
+  if (n >= (1ll << 26)) {
+    fprintf(stderr, "[graphgen] %s\n", what);
+    fflush(stderr);
+  }
+}
 
 inline uint64_t splitmix64(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
@@ -109,6 +118,7 @@ Graph *build_csr(int64_t n, int64_t nsamples, Emit emit) {
       c[v >> shift]++;
     }
   }
+  phase(n, "counted");
   std::vector<int64_t> boff((size_t)nb + 1);
   int64_t acc = 0;
   for (int64_t b = 0; b < nb; ++b) {
@@ -135,6 +145,7 @@ Graph *build_csr(int64_t n, int64_t nsamples, Emit emit) {
       pairs[c[v >> shift]++] = ((uint64_t)v << 32) | u;
     }
   }
+  phase(n, "scattered");
   // Sort + dedup each bucket; count unique entries per source vertex.
   std::vector<int64_t> deg((size_t)n + 1, 0);
   std::vector<int64_t> bkeep((size_t)nb, 0);
@@ -146,6 +157,7 @@ Graph *build_csr(int64_t n, int64_t nsamples, Emit emit) {
     bkeep[b] = k - s;
     for (uint64_t *p = s; p < k; ++p) deg[*p >> 32]++;
   }
+  phase(n, "sorted");
   g->row_ptr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
   if (!g->row_ptr) { free(pairs); delete g; return nullptr; }
   acc = 0;

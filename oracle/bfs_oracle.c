@@ -26,8 +26,20 @@
  * bit v lives in word v/64 at position v%64.
  */
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Progress lines on stderr for very large inputs (one per 1/16 of the work),
+ * so long runs show that they advance. */
+static void progress(const char *what, int64_t done, int64_t total) {
+  if (total < ((int64_t)1 << 26)) return;
+  const int64_t step = total / 16;
+  if (step > 0 && done % step == 0 && done > 0) {
+    fprintf(stderr, "[oracle] %s %lld/16\n", what, (long long)(done / step));
+    fflush(stderr);
+  }
+}
 
 /* FIFO BFS. dist must hold n entries. Returns the number of reached vertices,
  * or -1 if src is out of range or memory runs out. */
@@ -41,6 +53,7 @@ int64_t oracle_bfs(int64_t n, const int64_t *row_ptr, const int32_t *col, int64_
   dist[src] = 0;
   queue[tail++] = (int32_t)src;
   while (head < tail) {
+    progress("bfs", head, n);
     int32_t v = queue[head++];
     for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
       int32_t u = col[e];
@@ -131,6 +144,7 @@ int32_t oracle_stage(int64_t n, const int64_t *row_ptr, const int32_t *col, cons
   memset(local_out, 0, sizeof(uint64_t) * (size_t)(W * nlev));
   if (K > 0) memset(inc_out, 0, sizeof(uint64_t) * (size_t)(W * nlev * K));
   for (int64_t v = 0; v < n; ++v) {
+    progress("stage", v, n);
     int32_t L = dist[v];
     if (L < 0 || L >= nlev) continue;
     int32_t c = owner_of(v, P, bounds);

@@ -175,7 +175,12 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
   p->num_cus = prop.multiProcessorCount;
   p->coop = prop.cooperativeLaunch;
   int bpc = persistent_blocks_per_cu();
-  p->persist_grid = o->grid_blocks > 0 ? o->grid_blocks : p->num_cus * std::min(std::max(bpc, 1), 4);
+  p->persist_grid = o->grid_blocks > 0 ? o->grid_blocks : p->num_cus * std::min(std::max(bpc, 1), 2);
+  if (p->persist_grid > kBarrierGroup * kBarrierMaxGroups) {
+    g_create_error = "grid_blocks above the grid barrier's limit of 2048";
+    delete p;
+    return BFS_ERR_ARG;
+  }
   if (bpc <= 0 || p->persist_grid > bpc * p->num_cus) p->coop = 0;
   for (auto &ev : p->ev) {
     if (hipEventCreate(&ev) != hipSuccess) {

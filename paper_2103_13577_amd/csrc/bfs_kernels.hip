@@ -39,10 +39,10 @@ __global__ void __launch_bounds__(kBlock) k_reset(View v, int64_t src) {
     v.visited[i] = (i == sw) ? (1ull << (src & 63)) : 0ull;
     v.next[i] = 0ull;
   }
+  if (blockIdx.x == 0 && threadIdx.x < kBarrierMaxGroups) v.ctl->bar.group[threadIdx.x].count = 0;
   if (tid == 0) {
     Ctl *c = v.ctl;
-    c->bar.count = 0;
-    c->bar.gen = 0;
+    c->bar.top = 0;
     c->bar.tripped = 0;
     c->qn[0][0] = c->qn[0][1] = c->qn[1][0] = c->qn[1][1] = 0;
     c->heavy[0] = c->heavy[1] = 0;
@@ -82,22 +82,31 @@ __global__ void __launch_bounds__(kBlock) k_reset(View v, int64_t src) {
 // expand (Phase 1)
 // ---------------------------------------------------------------------------
 
-// Marks u in the next-frontier bitmap unless it is already visited. The
-// visited test is a plain load (visited does not change during expansion);
-// the cached read of `next` skips most redundant atomics.
-__device__ __forceinline__ void probe(const View &v, int32_t u) {
-  const uint32_t w = (uint32_t)u >> 6;
-  const uint64_t bit = 1ull << (u & 63);
-  if (v.visited[w] & bit) return;
-  if (v.next[w] & bit) return;
-  atomic_or_noret(v.next + w, bit);
-}
-
 // Streams adjacency entries with a non-temporal hint so the bitmaps keep
 // their place in L2.
 __device__ __forceinline__ int32_t load_col(const int32_t *col, int64_t e) {
   return __builtin_nontemporal_load(col + e);
 }
+
+// K independent probes: all visited words are requested before any is
+// tested, then all next words, so each lane keeps K random loads in flight.
+template <int K>
+__device__ __forceinline__ void probe_batch(const View &v, const int32_t (&u)[K],
+                                            const bool (&ok)[K]) {
+  uint64_t vis[K], nx[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) vis[j] = ok[j] ? v.visited[(uint32_t)u[j] >> 6] : ~0ull;
+  bool need[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) need[j] = !((vis[j] >> (u[j] & 63)) & 1ull);
+#pragma unroll
+  for (int j = 0; j < K; ++j) nx[j] = need[j] ? v.next[(uint32_t)u[j] >> 6] : ~0ull;
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+    if (!((nx[j] >> (u[j] & 63)) & 1ull)) atomic_or_noret(v.next + ((uint32_t)u[j] >> 6), 1ull << (u[j] & 63));
+}
+
+constexpr int kUnroll = 4;  // edges per lane in flight
 
 // Largest s in [0, n) with a[s] <= key (a ascending, a[0] == 0 <= key).
 __device__ __forceinline__ uint32_t upper_slot(const uint32_t *a, uint32_t n, uint64_t key) {
@@ -134,7 +143,17 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
     }
     __syncthreads();
     const int64_t lo = s_lo, hi = s_hi;
-    for (int64_t e = lo + threadIdx.x; e < hi; e += kBlock) probe(v, load_col(v.col, e));
+    for (int64_t e0 = lo + threadIdx.x; e0 < hi; e0 += kBlock * kUnroll) {
+      int32_t u[kUnroll];
+      bool ok[kUnroll];
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j) {
+        const int64_t e = e0 + (int64_t)j * kBlock;
+        ok[j] = e < hi;
+        u[j] = ok[j] ? load_col(v.col, e) : 0;
+      }
+      probe_batch<kUnroll>(v, u, ok);
+    }
     __syncthreads();
   }
 
@@ -143,7 +162,17 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
   for (uint64_t i = gwave; i < n1; i += nwaves) {
     const int64_t li = v.q1[cur][i] - v.vb;
     const int64_t b = v.rp[li], e = v.rp[li + 1];
-    for (int64_t k = b + lane; k < e; k += kWave) probe(v, load_col(v.col, k));
+    for (int64_t k0 = b + lane; k0 < e; k0 += kWave * kUnroll) {
+      int32_t u[kUnroll];
+      bool ok[kUnroll];
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j) {
+        const int64_t k = k0 + (int64_t)j * kWave;
+        ok[j] = k < e;
+        u[j] = ok[j] ? load_col(v.col, k) : 0;
+      }
+      probe_batch<kUnroll>(v, u, ok);
+    }
   }
 
   // Tier 0: 64 vertices per wavefront, their edges dealt evenly to the lanes.
@@ -161,18 +190,25 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
     const int64_t excl = incl - deg;
     // Every lane runs every step (the shuffles read all lanes); edge e of the
     // wavefront's batch belongs to the first lane k with incl[k] > e.
-    for (int64_t e0 = 0; e0 < total; e0 += kWave) {
-      const int64_t e = e0 + lane;
-      int k = 0;
+    for (int64_t e0 = 0; e0 < total; e0 += kWave * kUnroll) {
+      int32_t u[kUnroll];
+      bool ok[kUnroll];
 #pragma unroll
-      for (int step = 32; step >= 1; step >>= 1) {
-        const int64_t val = shfl64(incl, k + step - 1);
-        if (val <= e) k += step;
+      for (int j = 0; j < kUnroll; ++j) {
+        const int64_t e = e0 + (int64_t)j * kWave + lane;
+        int k = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+          const int64_t val = shfl64(incl, k + step - 1);
+          if (val <= e) k += step;
+        }
+        k = min(k, kWave - 1);
+        const int64_t xk = shfl64(excl, k);
+        const int64_t sk = shfl64(start, k);
+        ok[j] = e < total;
+        u[j] = ok[j] ? load_col(v.col, sk + (e - xk)) : 0;
       }
-      k = min(k, kWave - 1);
-      const int64_t xk = shfl64(excl, k);
-      const int64_t sk = shfl64(start, k);
-      if (e < total) probe(v, load_col(v.col, sk + (e - xk)));
+      probe_batch<kUnroll>(v, u, ok);
     }
   }
 }

@@ -114,6 +114,8 @@ void layout_batch(const bfs_graph *g, int32_t ng, const bfs_options *o, WsLayout
     for (int q = 0; q < 2; ++q) L.ms_q[t][q] = take(sizeof(int32_t) * (size_t)ntot);
   for (int q = 0; q < 2; ++q) L.ms_cstart[q] = take(sizeof(uint32_t) * (size_t)ntot);
   L.ms_extra = take(sizeof(int32_t) * nslot);
+  L.ms_mark = take(sizeof(int32_t) * (size_t)ntot);
+  L.ms_touched = take(sizeof(int32_t) * (size_t)ntot);
   L.ms_slot_out = take(sizeof(uint64_t) * nslot);
   L.ms_slot_type = take(sizeof(int32_t) * nslot);
   L.ms_slot_start = take(sizeof(int32_t) * nslot);
@@ -158,6 +160,9 @@ bfs_status batch_init(Plan *p) {
     v.cstart[q] = (uint32_t *)(w + L.ms_cstart[q]);
   }
   v.extra = (int32_t *)(w + L.ms_extra);
+  v.mark = (int32_t *)(w + L.ms_mark);
+  v.touched = (int32_t *)(w + L.ms_touched);
+  v.sparse_shift = 6;
   v.ctl = (MsCtl *)(w + L.ms_ctl);
   v.graphs = (const MsGraph *)(w + L.ms_graphs);
   v.slot_out = (uint64_t *)(w + L.ms_slot_out);
@@ -193,6 +198,8 @@ bfs_status batch_init(Plan *p) {
   if (e == hipSuccess) e = hipMemsetAsync(w + zero_from, 0, sizeof(MsCtl), p->stream);
   if (e == hipSuccess)
     e = hipMemsetAsync(w + L.ms_slot_active, 0, L.ms_admit - L.ms_slot_active, p->stream);
+  if (e == hipSuccess)  // no vertex has been touched at any level yet
+    e = hipMemsetAsync(w + L.ms_mark, 0xFF, sizeof(int32_t) * (size_t)L.ms_ntot, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) { delete b; return p->hip_fail(e, "batch state init"); }
   const size_t nslot = (size_t)ng * lw * 64;
@@ -305,7 +312,7 @@ bool BatchState::step(std::unique_lock<std::mutex> &lk) {
                        hipMemcpyHostToDevice, stream);
   MsView v = view;
   v.stream_stop = streaming ? 1 : 0;
-  const int max_levels = streaming ? (still_pending ? 8 : 64) : (1 << 30);
+  const int max_levels = streaming ? (still_pending ? 8 : 64) : (1 << 20);
   if (e == hipSuccess) e = ms_launch_persistent(v, max_levels, grid, stream);
   MsCtl ctl{};
   if (e == hipSuccess) e = hipMemcpyAsync(&ctl, view.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, stream);

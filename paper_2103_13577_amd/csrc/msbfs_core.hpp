@@ -31,12 +31,14 @@ struct MsCtl {
   uint32_t qn[2][2];      // tier-0/1 queue lengths by level parity
   uint64_t heavy[2];      // tier-2: (count << 40) | chunks, by parity
   uint64_t active[3];     // active vertices after the sweep of level L, by L mod 3
+  uint64_t gactive[3][kMsMaxGraphs];  // the same per graph
   uint32_t nextra;        // admitted sources to expand at the next level
+  uint32_t ntouched[2];   // touched vertices of sparse-mode graphs, by level parity
   int32_t level;          // next level to run (global clock of the batch engine)
   int32_t levels_run;     // levels completed by the last launch
   int32_t stopped_early;  // last launch ended because a slot finished
   int32_t err;
-  uint32_t pad;
+  int32_t sparse_levels;  // levels of the last launch run with a sparse graph
 };
 
 struct MsView {
@@ -50,6 +52,8 @@ struct MsView {
   int32_t *q0[2], *q1[2], *q2[2];
   uint32_t *cstart[2];
   int32_t *extra;            // admitted sources (flat ids)
+  int32_t *mark;             // [ntot] level at which a vertex was last touched
+  int32_t *touched;          // [ntot] touched vertices of sparse-mode graphs
   MsCtl *ctl;
   const MsGraph *graphs;     // [ng]
   uint64_t *slot_out;        // [ng*lw*64] device pointers of the outputs
@@ -60,6 +64,7 @@ struct MsView {
   uint64_t *depth_err;       // [ng*lw] uint8 slots whose depth exceeded 254
   int32_t small_bin, wave_bin, chunk_shift;
   int32_t stream_stop;       // stop a launch at the first level a slot finishes
+  int32_t sparse_shift;      // a graph runs sparse when active * 2^shift < n
 };
 
 // Admission record written by the host for each admitted query.

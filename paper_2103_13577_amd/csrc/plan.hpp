@@ -28,7 +28,7 @@ struct WsLayout {
   bool ms_on = false;
   int64_t ms_ntot = 0, ms_mtot = 0;
   size_t ms_ctl, ms_graphs, ms_rp, ms_col, ms_F, ms_N, ms_S;
-  size_t ms_q[3][2], ms_cstart[2], ms_extra;
+  size_t ms_q[3][2], ms_cstart[2], ms_extra, ms_mark, ms_touched;
   size_t ms_slot_out, ms_slot_type, ms_slot_start, ms_slot_active, ms_newmask, ms_depth_err;
   size_t ms_admit, ms_mask;
 };
