@@ -95,6 +95,10 @@ typedef struct {
   int32_t collect_stats;   /* nonzero: per-level frontier sizes and degree-bin histograms */
   bfs_exchange_fn exchange;
   void *exchange_ctx;
+  int32_t relabel;         /* whole graphs: 0 = automatic (on), 1 = on, -1 = off. A
+                              relabelled copy sorted by descending degree is built at plan
+                              creation (inside the workspace); results keep original ids */
+  int32_t reserved;
 } bfs_options;
 
 /* Fills *o with defaults (all zero / NULL, loop_mode AUTO). */
@@ -152,7 +156,8 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
  * exchange themselves.
  *   bfs_begin: reset (all distances infinity, root at 0, frontier {root} if
  *     owned) into dist (device int32[n_global], kept by the plan until the
- *     next bfs_begin).
+ *     next bfs_begin). The step-wise calls always work in the caller's vertex
+ *     ids (bitmaps included), never on the relabelled copy.
  *   bfs_expand: Phase 1 for the current level: every owned frontier vertex
  *     scans its adjacency and marks unvisited neighbours in the node's
  *     next-frontier bitmap. *local_next receives that bitmap's device address

@@ -42,7 +42,8 @@ class bfs_options(ctypes.Structure):
                 ("small_bin", ctypes.c_int32), ("wave_bin", ctypes.c_int32),
                 ("chunk_edges", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("batch_lanes", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
-                ("exchange", EXCHANGE_FN), ("exchange_ctx", ctypes.c_void_p)]
+                ("exchange", EXCHANGE_FN), ("exchange_ctx", ctypes.c_void_p),
+                ("relabel", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class bfs_stats(ctypes.Structure):
@@ -162,7 +163,8 @@ class Plan:
     """
 
     def __init__(self, graphs, *, loop_mode=LOOP_AUTO, small_bin=0, wave_bin=0, chunk_edges=0,
-                 grid_blocks=0, batch_lanes=0, collect_stats=False, exchange=None, stream=None):
+                 grid_blocks=0, batch_lanes=0, collect_stats=False, exchange=None, stream=None,
+                 relabel=0):
         torch = _torch()
         L = lib()
         if isinstance(graphs, DeviceGraph):
@@ -176,6 +178,7 @@ class Plan:
         o.loop_mode = loop_mode
         o.small_bin, o.wave_bin, o.chunk_edges = small_bin, wave_bin, chunk_edges
         o.grid_blocks, o.batch_lanes, o.collect_stats = grid_blocks, batch_lanes, int(collect_stats)
+        o.relabel = int(relabel)
         self._exchange_py = exchange
         self._exchange_keep = None
         if exchange is not None:

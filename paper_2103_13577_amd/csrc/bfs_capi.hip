@@ -67,8 +67,17 @@ View bfs_plan_s::view(int32_t gi, int32_t *dist) const {
   v.ve = g.v_end;
   v.m = g.m;
   v.words = (g.n_global + 63) / 64;
-  v.rp = g.row_ptr;
-  v.col = g.col;
+  if (cur_relabel && lay.rl_rp.size() > (size_t)gi && lay.rl_rp[gi]) {
+    v.rp = (const int64_t *)(b + lay.rl_rp[gi]);
+    v.col = (const int32_t *)(b + lay.rl_col[gi]);
+    v.old_id = (const int32_t *)(b + lay.rl_old[gi]);
+    v.new_id = (const int32_t *)(b + lay.rl_new[gi]);
+  } else {
+    v.rp = g.row_ptr;
+    v.col = g.col;
+    v.old_id = nullptr;
+    v.new_id = nullptr;
+  }
   v.dist = dist;
   v.visited = (uint64_t *)(b + lay.visited);
   v.next = (uint64_t *)(b + lay.next);
@@ -122,6 +131,7 @@ bfs_status bfs_workspace_size(const bfs_graph *graphs, int32_t ngraphs, const bf
   WsLayout L{};
   size_t off = 0;
   layout_single(graphs, ngraphs, L, off);
+  layout_relabel(graphs, ngraphs, o, L, off);
   layout_batch(graphs, ngraphs, o, L, off);
   *bytes = off;
   return BFS_OK;
@@ -164,6 +174,7 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
   p->stream = (hipStream_t)o->hip_stream;
   size_t off = 0;
   layout_single(graphs, ngraphs, p->lay, off);
+  layout_relabel(graphs, ngraphs, o, p->lay, off);
   layout_batch(graphs, ngraphs, o, p->lay, off);
   int dev = 0;
   hipDeviceProp_t prop;
@@ -193,6 +204,8 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
   if (st) { g_create_error = p->err; delete p; return st; }
   st = choose_tuning(p);
   if (st) { g_create_error = p->err; delete p; return st; }
+  st = relabel_graphs(p);
+  if (st) { g_create_error = p->err; delete p; return st; }
   st = batch_init(p);
   if (st) { g_create_error = p->err; delete p; return st; }
   *out = p;
@@ -210,8 +223,12 @@ const char *bfs_last_error(bfs_plan_t p) {
   return p->err.c_str();
 }
 
-bfs_status bfs_begin(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist) {
-  if (!p) return BFS_ERR_ARG;
+namespace {
+
+// Reset for a traversal. bfs_run may use the relabelled copy of a whole graph
+// (its bitmaps never leave the library); the step-wise calls work in caller
+// ids because their bitmaps are exchanged with other nodes.
+bfs_status begin_impl(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, bool relabel) {
   if (graph < 0 || graph >= (int32_t)p->graphs.size())
     return p->fail(BFS_ERR_ARG, "graph index out of range");
   const bfs_graph &g = p->graphs[graph];
@@ -222,6 +239,7 @@ bfs_status bfs_begin(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist)
   p->cur_graph = graph;
   p->cur_source = source;
   p->cur_dist = dist;
+  p->cur_relabel = relabel;
   p->level = 0;
   p->level_frontier.assign(1, (source >= g.v_begin && source < g.v_end) ? 1 : 0);
   View v = p->view(graph, dist);
@@ -231,6 +249,13 @@ bfs_status bfs_begin(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist)
   p->began = true;
   p->finished = false;
   return BFS_OK;
+}
+
+}  // namespace
+
+bfs_status bfs_begin(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist) {
+  if (!p) return BFS_ERR_ARG;
+  return begin_impl(p, graph, source, dist, false);
 }
 
 bfs_status bfs_expand(bfs_plan_t p, const uint64_t **local_next) {
@@ -316,7 +341,7 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   p->last_loop_ms = 0.f;
   e = hipEventRecord(ev0, p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
-  s = bfs_begin(p, graph, source, dist);
+  s = begin_impl(p, graph, source, dist, p->opt.exchange == nullptr);
   if (s) return s;
   const bfs_graph &g = p->graphs[graph];
   const bool host_loop = p->opt.exchange != nullptr || p->opt.loop_mode == BFS_LOOP_HOST ||

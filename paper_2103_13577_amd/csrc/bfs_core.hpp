@@ -38,7 +38,9 @@ struct View {
   int64_t words;    // ceil(n / 64)
   const int64_t *rp;
   const int32_t *col;
-  int32_t *dist;
+  const int32_t *old_id;  // relabelled graph: traversal id -> caller id (NULL: identity)
+  const int32_t *new_id;  // caller id -> traversal id (NULL: identity)
+  int32_t *dist;          // indexed by caller ids
   uint64_t *visited;
   uint64_t *next;
   int32_t *q0[2];

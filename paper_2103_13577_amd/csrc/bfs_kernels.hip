@@ -30,10 +30,12 @@ namespace bfsk {
 // reset
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock) k_reset(View v, int64_t src) {
+// src is a caller id; the traversal works on traversal ids (relabelled graphs).
+__global__ void __launch_bounds__(kBlock) k_reset(View v, int64_t src_caller) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = tid; i < v.n; i += stride) v.dist[i] = (i == src) ? 0 : -1;
+  for (int64_t i = tid; i < v.n; i += stride) v.dist[i] = (i == src_caller) ? 0 : -1;
+  const int64_t src = v.new_id ? (int64_t)v.new_id[src_caller] : src_caller;
   const int64_t sw = src >> 6;
   for (int64_t i = tid; i < v.words; i += stride) {
     v.visited[i] = (i == sw) ? (1ull << (src & 63)) : 0ull;
@@ -289,7 +291,7 @@ __device__ void merge_phase(const View &v, const MergeArgs &a, uint32_t vb_id, u
       const uint64_t wj = readlane64(nw, j);
       const uint64_t oj = readlane64(om, j);
       const int64_t vtx = (wbase + j) * 64 + lane;
-      if ((wj >> lane) & 1ull) v.dist[vtx] = dnew;
+      if ((wj >> lane) & 1ull) v.dist[v.old_id ? (int64_t)v.old_id[vtx] : vtx] = dnew;
       int t = 0;
       int64_t deg = 0;
       const bool own = (oj >> lane) & 1ull;
@@ -475,28 +477,32 @@ __global__ void __launch_bounds__(kBlock) k_persistent(View v, int max_levels) {
 // Canonical parents for the owned range: one wavefront per owned vertex takes
 // the smallest neighbour one level closer to the root. Non-owned reached
 // vertices get -2, unreached -1, the root itself.
+// x runs over traversal ids; parents and distances are in caller ids, and the
+// minimum is taken over caller ids.
 __global__ void __launch_bounds__(kBlock) k_parent(View v, int32_t *parent, int64_t src) {
   const int lane = lane_id();
   const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   for (int64_t x = gw; x < v.n; x += nw) {
-    const int32_t d = v.dist[x];
+    const int64_t xc = v.old_id ? (int64_t)v.old_id[x] : x;
+    const int32_t d = v.dist[xc];
     int32_t out;
     if (d < 0) out = -1;
-    else if (x == src) out = (int32_t)x;
+    else if (xc == src) out = (int32_t)xc;
     else if (x < v.vb || x >= v.ve) out = -2;
     else {
       const int64_t li = x - v.vb;
       int32_t best = 0x7fffffff;
       for (int64_t e = v.rp[li] + lane; e < v.rp[li + 1]; e += kWave) {
         const int32_t u = v.col[e];
-        if (u < best && v.dist[u] == d - 1) best = u;
+        const int32_t uc = v.old_id ? v.old_id[u] : u;
+        if (uc < best && v.dist[uc] == d - 1) best = uc;
       }
 #pragma unroll
       for (int s = 32; s >= 1; s >>= 1) best = min(best, __shfl_xor(best, s));
       out = best;
     }
-    if (lane == 0) parent[x] = out;
+    if (lane == 0) parent[xc] = out;
   }
 }
 

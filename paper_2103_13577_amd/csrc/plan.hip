@@ -7,6 +7,7 @@
 #include <string>
 
 #include "plan.hpp"
+#include "relabel.hpp"
 
 namespace bfsk {
 
@@ -53,6 +54,62 @@ bfs_status validate_graphs(Plan *p) {
       if (h & 8) why += " column id out of range";
       return p->fail(BFS_ERR_ARG, "graph " + std::to_string(i) + " invalid:" + why);
     }
+  }
+  return BFS_OK;
+}
+
+bool relabel_wanted(const bfs_graph &g, const bfs_options *o) {
+  const int32_t r = o ? o->relabel : 0;
+  if (r < 0) return false;
+  // whole graphs only (a share's ids are global and shared with other nodes);
+  // the sort helpers take 32-bit item counts
+  return g.v_begin == 0 && g.v_end == g.n_global && g.m < (1ll << 31) - 1 && g.n_global > 1;
+}
+
+void layout_relabel(const bfs_graph *g, int32_t ng, const bfs_options *o, WsLayout &L, size_t &off) {
+  auto take = [&](size_t bytes) {
+    size_t r = off;
+    off = (off + std::max<size_t>(bytes, 8) + 255) / 256 * 256;
+    return r;
+  };
+  L.rl_rp.assign(ng, 0);
+  L.rl_col.assign(ng, 0);
+  L.rl_old.assign(ng, 0);
+  L.rl_new.assign(ng, 0);
+  RelabelSizes mx{};
+  bool any = false;
+  for (int i = 0; i < ng; ++i) {
+    if (!relabel_wanted(g[i], o)) continue;
+    any = true;
+    L.rl_rp[i] = take(sizeof(int64_t) * (size_t)(g[i].n_global + 1));
+    L.rl_col[i] = take(sizeof(int32_t) * (size_t)g[i].m);
+    L.rl_old[i] = take(sizeof(int32_t) * (size_t)g[i].n_global);
+    L.rl_new[i] = take(sizeof(int32_t) * (size_t)g[i].n_global);
+    RelabelSizes s = relabel_sizes(g[i].n_global, g[i].m);
+    mx.keys = std::max(mx.keys, s.keys);
+    mx.tmp_col = std::max(mx.tmp_col, s.tmp_col);
+    mx.temp = std::max(mx.temp, s.temp);
+  }
+  if (!any) return;
+  L.rl_keys_a = take(mx.keys);
+  L.rl_keys_b = take(mx.keys);
+  L.rl_tmp_col = take(mx.tmp_col);
+  L.rl_temp = take(mx.temp);
+  L.rl_temp_bytes = mx.temp;
+}
+
+bfs_status relabel_graphs(Plan *p) {
+  char *w = (char *)p->ws;
+  for (size_t i = 0; i < p->graphs.size(); ++i) {
+    if (!p->lay.rl_rp[i]) continue;
+    const bfs_graph &g = p->graphs[i];
+    hipError_t e = relabel_build(g.row_ptr, g.col, g.n_global, g.m, (int64_t *)(w + p->lay.rl_rp[i]),
+                                 (int32_t *)(w + p->lay.rl_col[i]), (int32_t *)(w + p->lay.rl_old[i]),
+                                 (int32_t *)(w + p->lay.rl_new[i]), w + p->lay.rl_keys_a,
+                                 w + p->lay.rl_keys_b, w + p->lay.rl_tmp_col, w + p->lay.rl_temp,
+                                 p->lay.rl_temp_bytes, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "relabel");
   }
   return BFS_OK;
 }

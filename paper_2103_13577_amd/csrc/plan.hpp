@@ -25,6 +25,10 @@ struct WsLayout {
   size_t q[3][2];
   size_t cstart[2];
   // batched multi-source state (see msbfs_core.hpp)
+  // relabelled copies (per graph; 0 when the graph is not relabelled) and
+  // plan-time scratch for building them
+  std::vector<size_t> rl_rp, rl_col, rl_old, rl_new;
+  size_t rl_keys_a = 0, rl_keys_b = 0, rl_tmp_col = 0, rl_temp = 0, rl_temp_bytes = 0;
   bool ms_on = false;
   int64_t ms_ntot = 0, ms_mtot = 0;
   size_t ms_ctl, ms_graphs, ms_rp, ms_col, ms_F, ms_N, ms_S;
@@ -64,6 +68,7 @@ struct bfs_plan_s {
   int32_t cur_graph = 0;
   int64_t cur_source = 0;
   int32_t *cur_dist = nullptr;
+  bool cur_relabel = false;  // the current traversal runs on the relabelled copy
   int32_t level = 0;
   int32_t persistent_levels = 0;
   int64_t last_level_new = 0;
@@ -90,6 +95,9 @@ namespace bfsk {
 using Plan = bfs_plan_s;
 
 void layout_single(const bfs_graph *g, int32_t ng, WsLayout &L, size_t &off);
+void layout_relabel(const bfs_graph *g, int32_t ng, const bfs_options *o, WsLayout &L, size_t &off);
+bool relabel_wanted(const bfs_graph &g, const bfs_options *o);
+bfs_status relabel_graphs(Plan *p);
 void layout_batch(const bfs_graph *g, int32_t ng, const bfs_options *o, WsLayout &L, size_t &off);
 bfs_status validate_graphs(Plan *p);
 bfs_status choose_tuning(Plan *p);

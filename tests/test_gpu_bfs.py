@@ -43,7 +43,10 @@ SMALL_GRAPHS = [
 MODES = [dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST),
          # tiny thresholds push vertices into the wavefront and chunked tiers
          dict(loop_mode=pkg.LOOP_PERSISTENT, small_bin=2, wave_bin=4, chunk_edges=64),
-         dict(loop_mode=pkg.LOOP_HOST, small_bin=1, wave_bin=1, chunk_edges=64)]
+         dict(loop_mode=pkg.LOOP_HOST, small_bin=1, wave_bin=1, chunk_edges=64),
+         # the caller's labels, without the degree-sorted copy
+         dict(loop_mode=pkg.LOOP_PERSISTENT, relabel=-1),
+         dict(loop_mode=pkg.LOOP_HOST, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64)]
 
 
 @pytest.mark.parametrize("name,make,sources", SMALL_GRAPHS, ids=[x[0] for x in SMALL_GRAPHS])
