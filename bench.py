@@ -138,7 +138,7 @@ def run_single(args, name, scale, ef):
                                f"(A=.57,B=.19,C=.19), symmetrised, int32 CSR, "
                                f"{args.steps} seeded sources one at a time",
                    "n": g.n, "m_directed": g.m, "sources": args.steps,
-                   "loop_mode": args.loop_mode},
+                   "plan": plan.tuning(0)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "kernel": "k_persistent",

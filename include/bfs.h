@@ -98,7 +98,11 @@ typedef struct {
   int32_t relabel;         /* whole graphs: 0 = automatic (on), 1 = on, -1 = off. A
                               relabelled copy sorted by descending degree is built at plan
                               creation (inside the workspace); results keep original ids */
-  int32_t reserved;
+  int32_t autotune;        /* 0 = automatic (whole graphs with >= 2^22 edges), 1 = always,
+                              -1 = never. The plan times a few traversals per candidate
+                              (level loop, register budget, grid size, degree-bin tier
+                              thresholds) and keeps the fastest; explicit option values
+                              are never overridden */
 } bfs_options;
 
 /* Fills *o with defaults (all zero / NULL, loop_mode AUTO). */
@@ -138,6 +142,21 @@ void bfs_plan_destroy(bfs_plan_t p);
 
 /* Last error message of the plan (or of the last failed create when p is NULL). */
 const char *bfs_last_error(bfs_plan_t p);
+
+/* Settings the plan uses for one graph (after autotuning). */
+typedef struct {
+  int32_t loop_mode;        /* BFS_LOOP_HOST or BFS_LOOP_PERSISTENT */
+  int32_t persist_variant;  /* 0: default registers, 1: 64-VGPR budget */
+  int32_t grid_blocks;      /* blocks of the persistent launch */
+  int32_t small_bin;
+  int32_t wave_bin;
+  int32_t chunk_edges;
+  int32_t relabelled;       /* 1 if bfs_run traverses the degree-sorted copy */
+  float tuned_ms;           /* best traversal time seen by the autotuner (0: not tuned) */
+} bfs_tuning;
+
+/* Fills *out (host) with the settings of graph `graph`. */
+bfs_status bfs_plan_tuning(bfs_plan_t p, int32_t graph, bfs_tuning *out);
 
 /*
  * Single-source traversal (Algorithm 1; Algorithm 2 when the graph is a

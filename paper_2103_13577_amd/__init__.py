@@ -43,13 +43,20 @@ class bfs_options(ctypes.Structure):
                 ("chunk_edges", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("batch_lanes", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
                 ("exchange", EXCHANGE_FN), ("exchange_ctx", ctypes.c_void_p),
-                ("relabel", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("relabel", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 class bfs_stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("reached", ctypes.c_int64),
                 ("edges_scanned", ctypes.c_int64), ("ms", ctypes.c_float),
                 ("loop_ms", ctypes.c_float)]
+
+
+class bfs_tuning(ctypes.Structure):
+    _fields_ = [("loop_mode", ctypes.c_int32), ("persist_variant", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("small_bin", ctypes.c_int32),
+                ("wave_bin", ctypes.c_int32), ("chunk_edges", ctypes.c_int32),
+                ("relabelled", ctypes.c_int32), ("tuned_ms", ctypes.c_float)]
 
 
 class bfs_query(ctypes.Structure):
@@ -90,6 +97,7 @@ def lib():
                                      ctypes.POINTER(i64)]),
         "bfs_finish": (i32, [vp, vp, ctypes.POINTER(bfs_stats)]),
         "bfs_level_stats": (i32, [vp, vp, vp, i32, ctypes.POINTER(i32)]),
+        "bfs_plan_tuning": (i32, [vp, i32, ctypes.POINTER(bfs_tuning)]),
         "bfs_batch_submit": (i32, [vp, ctypes.POINTER(bfs_query), i32, u32, ctypes.POINTER(u64)]),
         "bfs_batch_wait": (i32, [vp, u64, i64, ctypes.POINTER(bfs_batch_result)]),
         "bfs_batch_times": (i32, [vp, u64, vp, i32]),
@@ -104,8 +112,8 @@ def lib():
 
 EXPORTED = ("bfs_options_default", "bfs_workspace_size", "bfs_plan_create", "bfs_plan_destroy",
             "bfs_last_error", "bfs_run", "bfs_begin", "bfs_expand", "bfs_merge_frontier",
-            "bfs_finish", "bfs_level_stats", "bfs_batch_submit", "bfs_batch_wait",
-            "bfs_batch_times")
+            "bfs_finish", "bfs_level_stats", "bfs_plan_tuning", "bfs_batch_submit",
+            "bfs_batch_wait", "bfs_batch_times")
 
 
 class BfsError(RuntimeError):
@@ -164,7 +172,7 @@ class Plan:
 
     def __init__(self, graphs, *, loop_mode=LOOP_AUTO, small_bin=0, wave_bin=0, chunk_edges=0,
                  grid_blocks=0, batch_lanes=0, collect_stats=False, exchange=None, stream=None,
-                 relabel=0):
+                 relabel=0, autotune=0):
         torch = _torch()
         L = lib()
         if isinstance(graphs, DeviceGraph):
@@ -179,6 +187,7 @@ class Plan:
         o.small_bin, o.wave_bin, o.chunk_edges = small_bin, wave_bin, chunk_edges
         o.grid_blocks, o.batch_lanes, o.collect_stats = grid_blocks, batch_lanes, int(collect_stats)
         o.relabel = int(relabel)
+        o.autotune = int(autotune)
         self._exchange_py = exchange
         self._exchange_keep = None
         if exchange is not None:
@@ -271,6 +280,12 @@ class Plan:
         self._check(lib().bfs_finish(self.h, parent.data_ptr() if parent is not None else None,
                                      ctypes.byref(st)))
         return Stats(st.levels, st.reached, st.edges_scanned, st.ms, st.loop_ms)
+
+    def tuning(self, graph: int = 0) -> dict:
+        """Settings the plan uses for one graph (after autotuning)."""
+        t = bfs_tuning()
+        self._check(lib().bfs_plan_tuning(self.h, graph, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in bfs_tuning._fields_}
 
     def level_stats(self):
         """(frontier sizes per level, degree-bin histogram [levels, 34])."""

@@ -1,0 +1,147 @@
+// Plan-time autotuner: times a few whole traversals per candidate setting on
+// the plan's own graph and keeps the fastest. Candidates: the level loop
+// (host-driven launches per phase, or the cooperative persistent loop with
+// either register budget and grid size) and the degree-bin thresholds that
+// split the frontier into the lane-group, wavefront and workgroup tiers.
+// Settings given explicitly in the options are never changed.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace bfsk {
+
+namespace {
+
+bool tune_wanted(const Plan *p, size_t gi) {
+  const int a = p->opt.autotune;
+  if (a < 0 || p->opt.exchange) return false;
+  const bfs_graph &g = p->graphs[gi];
+  if (g.v_begin != 0 || g.v_end != g.n_global) return false;
+  if (a == 0 && g.m < (1ll << 22)) return false;
+  return true;
+}
+
+// A source with at least one edge, in caller ids: the highest-degree vertex
+// when the graph is relabelled, else the first vertex with an edge.
+bfs_status pick_source(Plan *p, size_t gi, int64_t &src) {
+  const bfs_graph &g = p->graphs[gi];
+  src = 0;
+  if (p->lay.rl_old[gi]) {
+    int32_t v = 0;
+    hipError_t e = hipMemcpy(&v, (char *)p->ws + p->lay.rl_old[gi], sizeof(int32_t),
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return p->hip_fail(e, "autotune source");
+    src = v;
+    return BFS_OK;
+  }
+  const int64_t cnt = std::min<int64_t>(g.n_global, 1 << 16);
+  std::vector<int64_t> rp((size_t)cnt + 1);
+  hipError_t e = hipMemcpy(rp.data(), g.row_ptr, sizeof(int64_t) * (cnt + 1), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return p->hip_fail(e, "autotune source");
+  for (int64_t v = 0; v < cnt; ++v)
+    if (rp[v + 1] > rp[v]) { src = v; break; }
+  return BFS_OK;
+}
+
+// Median of three timed traversals after one warm-up.
+bfs_status time_config(Plan *p, int32_t gi, int64_t src, float &ms) {
+  int32_t *dist = (int32_t *)((char *)p->ws + p->lay.tune_dist);
+  bfs_stats st;
+  bfs_status s = bfs_run(p, gi, src, dist, nullptr, &st);
+  if (s) return s;
+  float t[3];
+  for (float &x : t) {
+    s = bfs_run(p, gi, src, dist, nullptr, &st);
+    if (s) return s;
+    x = st.ms;
+  }
+  std::sort(t, t + 3);
+  ms = t[1];
+  return BFS_OK;
+}
+
+}  // namespace
+
+bfs_status autotune_graphs(Plan *p) {
+  for (size_t gi = 0; gi < p->graphs.size(); ++gi) {
+    if (!tune_wanted(p, gi) || !p->lay.tune_dist) continue;
+    int64_t src = 0;
+    bfs_status s = pick_source(p, gi, src);
+    if (s) return s;
+    Tuning &t = p->tune[gi];
+    Tuning best = t;
+    float best_ms = 1e30f;
+    auto trial = [&](const Tuning &c) -> bfs_status {
+      const Tuning keep = t;
+      t = c;
+      float ms = 0.f;
+      bfs_status r = time_config(p, (int32_t)gi, src, ms);
+      if (r == BFS_OK && ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+      t = keep;
+      return r;
+    };
+    // 1. level loop, register budget and grid size
+    std::vector<Tuning> loops;
+    if (p->opt.loop_mode == BFS_LOOP_AUTO) {
+      Tuning h = t;
+      h.loop_mode = BFS_LOOP_HOST;
+      loops.push_back(h);
+    }
+    if (p->coop && p->opt.loop_mode != BFS_LOOP_HOST) {
+      for (int var = 0; var < 2; ++var) {
+        const int bpc = p->bpc[var];
+        for (int per_cu : {bpc, bpc / 2}) {
+          const int grid = std::min(per_cu * p->num_cus, kBarrierGroup * kBarrierMaxGroups);
+          if (per_cu <= 0 || grid <= 0) continue;
+          Tuning c = t;
+          c.loop_mode = BFS_LOOP_PERSISTENT;
+          c.persist_variant = var;
+          c.persist_grid = p->persist_grid > 0 ? p->persist_grid : grid;
+          loops.push_back(c);
+          if (p->persist_grid > 0) break;
+        }
+      }
+    }
+    if (loops.empty()) loops.push_back(t);
+    for (const Tuning &c : loops)
+      if ((s = trial(c))) return s;
+    t = best;
+    // 2. tier thresholds (degree bins), each kept only if it helps
+    if (p->opt.small_bin <= 0)
+      for (int sb : {4, 5, 7}) {
+        Tuning c = best;
+        c.small_bin = sb;
+        if (c.wave_bin < sb) continue;
+        if ((s = trial(c))) return s;
+      }
+    t = best;
+    if (p->opt.wave_bin <= 0)
+      for (int wb : {11, 15}) {
+        Tuning c = best;
+        c.wave_bin = std::max(wb, c.small_bin);
+        const int64_t heavy_max = std::min<int64_t>(p->graphs[gi].n_global,
+                                                    (p->graphs[gi].m >> (c.wave_bin - 1)) + 1);
+        if (heavy_max >= (1ll << (64 - kHeavyShift))) continue;
+        if ((s = trial(c))) return s;
+      }
+    t = best;
+    if (p->opt.chunk_edges <= 0)
+      for (int cs : {11, 13}) {
+        Tuning c = best;
+        c.chunk_shift = cs;
+        if ((s = trial(c))) return s;
+      }
+    t = best;
+    t.tuned_ms = best_ms;
+  }
+  return BFS_OK;
+}
+
+}  // namespace bfsk

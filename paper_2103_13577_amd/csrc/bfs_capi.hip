@@ -52,8 +52,8 @@ void layout_single(const bfs_graph *g, int32_t ng, WsLayout &L, size_t &off) {
   L.visited = off; off = align_up(off + sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), 256);
   L.next = off; off = align_up(off + sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), 256);
   for (int t = 0; t < 3; ++t)
-    for (int p = 0; p < 2; ++p) { L.q[t][p] = off; off = align_up(off + sizeof(int32_t) * (size_t)omax, 256); }
-  for (int p = 0; p < 2; ++p) { L.cstart[p] = off; off = align_up(off + sizeof(uint32_t) * (size_t)omax, 256); }
+    for (int p = 0; p < kRing; ++p) { L.q[t][p] = off; off = align_up(off + sizeof(int32_t) * (size_t)omax, 256); }
+  for (int p = 0; p < kRing; ++p) { L.cstart[p] = off; off = align_up(off + sizeof(uint32_t) * (size_t)omax, 256); }
 }
 
 }  // namespace bfsk
@@ -81,7 +81,7 @@ View bfs_plan_s::view(int32_t gi, int32_t *dist) const {
   v.dist = dist;
   v.visited = (uint64_t *)(b + lay.visited);
   v.next = (uint64_t *)(b + lay.next);
-  for (int p = 0; p < 2; ++p) {
+  for (int p = 0; p < kRing; ++p) {
     v.q0[p] = (int32_t *)(b + lay.q[0][p]);
     v.q1[p] = (int32_t *)(b + lay.q[1][p]);
     v.q2[p] = (int32_t *)(b + lay.q[2][p]);
@@ -94,6 +94,7 @@ View bfs_plan_s::view(int32_t gi, int32_t *dist) const {
   v.wave_bin = tune[gi].wave_bin;
   v.chunk_shift = tune[gi].chunk_shift;
   v.stats = opt.collect_stats ? 1 : 0;
+  v.sparse_div = tune[gi].sparse_div;
   return v;
 }
 
@@ -185,14 +186,14 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
   }
   p->num_cus = prop.multiProcessorCount;
   p->coop = prop.cooperativeLaunch;
-  int bpc = persistent_blocks_per_cu();
-  p->persist_grid = o->grid_blocks > 0 ? o->grid_blocks : p->num_cus * std::min(std::max(bpc, 1), 2);
-  if (p->persist_grid > kBarrierGroup * kBarrierMaxGroups) {
+  p->bpc[0] = persistent_blocks_per_cu(0);
+  p->bpc[1] = persistent_blocks_per_cu(1);
+  p->persist_grid = o->grid_blocks;  // 0: chosen per graph
+  if (o->grid_blocks > kBarrierGroup * kBarrierMaxGroups) {
     g_create_error = "grid_blocks above the grid barrier's limit of 2048";
     delete p;
     return BFS_ERR_ARG;
   }
-  if (bpc <= 0 || p->persist_grid > bpc * p->num_cus) p->coop = 0;
   for (auto &ev : p->ev) {
     if (hipEventCreate(&ev) != hipSuccess) {
       g_create_error = "hipEventCreate failed";
@@ -205,6 +206,8 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
   st = choose_tuning(p);
   if (st) { g_create_error = p->err; delete p; return st; }
   st = relabel_graphs(p);
+  if (st) { g_create_error = p->err; delete p; return st; }
+  st = autotune_graphs(p);
   if (st) { g_create_error = p->err; delete p; return st; }
   st = batch_init(p);
   if (st) { g_create_error = p->err; delete p; return st; }
@@ -241,6 +244,7 @@ bfs_status begin_impl(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist
   p->cur_dist = dist;
   p->cur_relabel = relabel;
   p->level = 0;
+  p->expanded_level = -1;
   p->level_frontier.assign(1, (source >= g.v_begin && source < g.v_end) ? 1 : 0);
   View v = p->view(graph, dist);
   int grid = (int)std::min<int64_t>((g.n_global + kBlock - 1) / kBlock, (int64_t)p->num_cus * 16);
@@ -266,8 +270,10 @@ bfs_status bfs_expand(bfs_plan_t p, const uint64_t **local_next) {
     hipError_t e = launch_clear_stats_row(v, p->level + 1, p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "stats launch");
   }
+  if (p->expanded_level == p->level) return p->fail(BFS_ERR_STATE, "level already expanded");
   hipError_t e = launch_expand(v, p->level, p->wide_grid(), p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "expand launch");
+  p->expanded_level = p->level;
   if (local_next) *local_next = v.next;
   return BFS_OK;
 }
@@ -276,6 +282,7 @@ bfs_status bfs_merge_frontier(bfs_plan_t p, const uint64_t *const *incoming, int
                               int32_t keep_next, int64_t *global_new, int64_t *owned_new) {
   if (!p) return BFS_ERR_ARG;
   if (!p->began || p->finished) return p->fail(BFS_ERR_STATE, "bfs_merge_frontier before bfs_begin");
+  if (p->expanded_level != p->level) return p->fail(BFS_ERR_STATE, "bfs_merge_frontier before bfs_expand of this level");
   if (k < 0 || (k > 0 && !incoming)) return p->fail(BFS_ERR_ARG, "bad incoming list");
   for (int i = 0; i < k; ++i)
     if (!incoming[i]) return p->fail(BFS_ERR_ARG, "incoming bitmap " + std::to_string(i) + " is NULL");
@@ -344,16 +351,27 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   s = begin_impl(p, graph, source, dist, p->opt.exchange == nullptr);
   if (s) return s;
   const bfs_graph &g = p->graphs[graph];
-  const bool host_loop = p->opt.exchange != nullptr || p->opt.loop_mode == BFS_LOOP_HOST ||
-                         (p->opt.loop_mode == BFS_LOOP_AUTO && !p->coop);
-  if (p->opt.loop_mode == BFS_LOOP_PERSISTENT && (!p->coop || p->opt.exchange))
-    return p->fail(BFS_ERR_ARG, "persistent loop needs cooperative launch and no exchange callback");
+  const Tuning &tu = p->tune[graph];
+  int mode = p->opt.loop_mode == BFS_LOOP_AUTO ? tu.loop_mode : p->opt.loop_mode;
+  if (p->opt.exchange) mode = BFS_LOOP_HOST;
+  int grid = 0;
+  if (mode == BFS_LOOP_PERSISTENT) {
+    grid = p->persist_grid > 0 ? p->persist_grid : tu.persist_grid;
+    const int cap = p->bpc[tu.persist_variant] * p->num_cus;
+    if (!p->coop || grid <= 0 || grid > cap) {
+      if (p->opt.loop_mode == BFS_LOOP_PERSISTENT)
+        return p->fail(BFS_ERR_ARG, "persistent loop needs a cooperative launch of at most " +
+                                        std::to_string(cap) + " blocks");
+      mode = BFS_LOOP_HOST;
+    }
+  }
+  const bool host_loop = mode != BFS_LOOP_PERSISTENT;
   if (!host_loop) {
     View v = p->view(graph, dist);
     const int max_levels = (int)std::min<int64_t>(g.n_global + 1, 1ll << 30);
     e = hipEventRecord(p->ev[2], p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
-    e = launch_persistent(v, max_levels, p->persist_grid, p->stream);
+    e = launch_persistent(v, max_levels, grid, tu.persist_variant, p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "persistent launch");
     e = hipEventRecord(ev1, p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
@@ -396,6 +414,22 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   p->last_ms = ms;
   p->last_loop_ms = lms;
   return bfs_finish(p, parent, st);
+}
+
+bfs_status bfs_plan_tuning(bfs_plan_t p, int32_t graph, bfs_tuning *out) {
+  if (!p) return BFS_ERR_ARG;
+  if (graph < 0 || graph >= (int32_t)p->graphs.size() || !out)
+    return p->fail(BFS_ERR_ARG, "bad graph index or NULL output");
+  const Tuning &t = p->tune[graph];
+  out->loop_mode = t.loop_mode;
+  out->persist_variant = t.persist_variant;
+  out->grid_blocks = p->persist_grid > 0 ? p->persist_grid : t.persist_grid;
+  out->small_bin = t.small_bin;
+  out->wave_bin = t.wave_bin;
+  out->chunk_edges = 1 << t.chunk_shift;
+  out->relabelled = (p->lay.rl_rp.size() > (size_t)graph && p->lay.rl_rp[graph]) ? 1 : 0;
+  out->tuned_ms = t.tuned_ms;
+  return BFS_OK;
 }
 
 bfs_status bfs_level_stats(bfs_plan_t p, int64_t *frontier, int64_t *hist, int32_t max_levels,

@@ -17,10 +17,12 @@ constexpr int kHeavyShift = 40;  // packed heavy-tier counter: count << 40 | chu
 constexpr uint64_t kChunkMask = (1ull << kHeavyShift) - 1;
 
 // Device control block at the start of the workspace.
+constexpr int kRing = 3;  // frontier queues rotate over level mod 3
+
 struct Ctl {
   GridBarrier bar;
-  uint32_t qn[2][2];      // tier-0 and tier-1 queue lengths, by level parity
-  uint64_t heavy[2];      // tier-2 queue: (count << 40) | total chunks, by parity
+  uint32_t qn[kRing][2];  // tier-0 and tier-1 queue lengths, by level mod 3
+  uint64_t heavy[kRing];  // tier-2 queue: (count << 40) | total chunks, by level mod 3
   uint64_t newcnt[3];     // vertices new in the level (all ranges), by level mod 3
   uint64_t ownedcnt[3];   // owned vertices new in the level, by level mod 3
   uint64_t edges;         // sum of degrees over every enqueued owned vertex
@@ -43,10 +45,10 @@ struct View {
   int32_t *dist;          // indexed by caller ids
   uint64_t *visited;
   uint64_t *next;
-  int32_t *q0[2];
-  int32_t *q1[2];
-  int32_t *q2[2];
-  uint32_t *cstart[2];
+  int32_t *q0[kRing];
+  int32_t *q1[kRing];
+  int32_t *q2[kRing];
+  uint32_t *cstart[kRing];
   Ctl *ctl;
   int64_t *lvl_frontier;  // [kMaxStatLevels]
   uint32_t *lvl_hist;     // [kMaxStatLevels * kNumBins]
@@ -54,6 +56,9 @@ struct View {
   int32_t wave_bin;       // bins < wave_bin -> tier 1, else tier 2
   int32_t chunk_shift;    // tier-2 work item = 2^chunk_shift edges
   int32_t stats;
+  int32_t sparse_div;     // device loop: a level runs queue-only when the
+                          // frontier is below words / sparse_div (0 = never)
+  int32_t pad;
 };
 
 constexpr int kMaxIncoming = 8;  // received bitmaps per merge launch
@@ -84,7 +89,7 @@ hipError_t launch_expand(const View &v, int level, int grid, hipStream_t s);
 hipError_t launch_merge(const View &v, const MergeArgs &a, int grid, hipStream_t s);
 hipError_t launch_clear_stats_row(const View &v, int level, hipStream_t s);
 hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, hipStream_t s);
-hipError_t launch_persistent(const View &v, int max_levels, int grid, hipStream_t s);
-int persistent_blocks_per_cu();
+hipError_t launch_persistent(const View &v, int max_levels, int grid, int variant, hipStream_t s);
+int persistent_blocks_per_cu(int variant);
 
 }  // namespace bfsk

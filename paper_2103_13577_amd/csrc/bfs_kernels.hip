@@ -46,8 +46,10 @@ __global__ void __launch_bounds__(kBlock) k_reset(View v, int64_t src_caller) {
     Ctl *c = v.ctl;
     c->bar.top = 0;
     c->bar.tripped = 0;
-    c->qn[0][0] = c->qn[0][1] = c->qn[1][0] = c->qn[1][1] = 0;
-    c->heavy[0] = c->heavy[1] = 0;
+    for (int r = 0; r < kRing; ++r) {
+      c->qn[r][0] = c->qn[r][1] = 0;
+      c->heavy[r] = 0;
+    }
     for (int k = 0; k < 3; ++k) c->newcnt[k] = c->ownedcnt[k] = 0;
     c->edges = 0;
     c->reached = 1;
@@ -74,7 +76,7 @@ __global__ void __launch_bounds__(kBlock) k_reset(View v, int64_t src_caller) {
     }
     if (v.stats) {
       v.lvl_frontier[0] = owned ? 1 : 0;
-      for (int b = 0; b < kNumBins; ++b) v.lvl_hist[b] = 0;
+      for (int b = 0; b < 2 * kNumBins; ++b) v.lvl_hist[b] = 0;  // rows 0 and 1
       if (owned) v.lvl_hist[degree_bin(deg)] = 1;
     }
   }
@@ -108,7 +110,85 @@ __device__ __forceinline__ void probe_batch(const View &v, const int32_t (&u)[K]
     if (!((nx[j] >> (u[j] & 63)) & 1ull)) atomic_or_noret(v.next + ((uint32_t)u[j] >> 6), 1ull << (u[j] & 63));
 }
 
+// Per-lane totals of a queue-only level, reduced once per workgroup.
+struct SparseAcc {
+  uint64_t nnew = 0, owned = 0, edges = 0;
+};
+
+// Queue-only level (single node, small frontier): the atomic OR goes straight
+// into `visited`; the lane whose OR flipped the bit owns the vertex: it writes
+// the distance and appends the vertex to its tier queue for the next level.
+// All lanes of the wavefront must call this (the appends use ballots).
+template <int K>
+__device__ __forceinline__ void probe_batch_sparse(const View &v, const int32_t (&u)[K],
+                                                   const bool (&ok)[K], int L, SparseAcc &acc) {
+  const int nxt = (L + 1) % kRing;
+  const int lane = lane_id();
+  uint64_t vis[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) vis[j] = ok[j] ? v.visited[(uint32_t)u[j] >> 6] : ~0ull;
+  bool win[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint64_t bit = 1ull << (u[j] & 63);
+    win[j] = false;
+    if (!(vis[j] & bit)) win[j] = !(atomic_or64(v.visited + ((uint32_t)u[j] >> 6), bit) & bit);
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    int64_t deg = 0;
+    int t = 0;
+    bool own = false;
+    if (win[j]) {
+      const int64_t x = u[j];
+      v.dist[v.old_id ? (int64_t)v.old_id[x] : x] = L + 1;
+      acc.nnew += 1;
+      own = x >= v.vb && x < v.ve;
+      if (own) {
+        const int64_t li = x - v.vb;
+        deg = v.rp[li + 1] - v.rp[li];
+        const int b = degree_bin(deg);
+        t = tier_of_bin(b, v.small_bin, v.wave_bin);
+        acc.owned += 1;
+        acc.edges += (uint64_t)deg;
+        if (v.stats && L + 1 < kMaxStatLevels) atomic_add32(&v.lvl_hist[(L + 1) * kNumBins + b], 1u);
+      }
+    }
+    const uint64_t m0 = ballot(own && t == 0);
+    const uint64_t m1 = ballot(own && t == 1);
+    if (m0) {
+      const int ld = __ffsll((unsigned long long)m0) - 1;
+      uint32_t base = 0;
+      if (lane == ld) base = atomic_add32(&v.ctl->qn[nxt][0], (uint32_t)__popcll(m0));
+      base = __builtin_amdgcn_readlane(base, ld);
+      if (own && t == 0) v.q0[nxt][base + rank_below(m0)] = u[j];
+    }
+    if (m1) {
+      const int ld = __ffsll((unsigned long long)m1) - 1;
+      uint32_t base = 0;
+      if (lane == ld) base = atomic_add32(&v.ctl->qn[nxt][1], (uint32_t)__popcll(m1));
+      base = __builtin_amdgcn_readlane(base, ld);
+      if (own && t == 1) v.q1[nxt][base + rank_below(m1)] = u[j];
+    }
+    if (own && t == 2) {
+      // one packed atomic per hub keeps slot order and chunk starts monotone
+      const uint64_t nch = (uint64_t)((deg + (1ll << v.chunk_shift) - 1) >> v.chunk_shift);
+      const uint64_t old = atomic_add64(&v.ctl->heavy[nxt], (1ull << kHeavyShift) | nch);
+      const uint32_t slot = (uint32_t)(old >> kHeavyShift);
+      v.q2[nxt][slot] = u[j];
+      v.cstart[nxt][slot] = (uint32_t)(old & kChunkMask);
+    }
+  }
+}
+
 constexpr int kUnroll = 4;  // edges per lane in flight
+
+template <bool SPARSE>
+__device__ __forceinline__ void probe_dispatch(const View &v, const int32_t (&u)[kUnroll],
+                                               const bool (&ok)[kUnroll], int L, SparseAcc &acc) {
+  if (SPARSE) probe_batch_sparse<kUnroll>(v, u, ok, L, acc);
+  else probe_batch<kUnroll>(v, u, ok);
+}
 
 // Largest s in [0, n) with a[s] <= key (a ascending, a[0] == 0 <= key).
 __device__ __forceinline__ uint32_t upper_slot(const uint32_t *a, uint32_t n, uint64_t key) {
@@ -120,14 +200,29 @@ __device__ __forceinline__ uint32_t upper_slot(const uint32_t *a, uint32_t n, ui
   return lo;
 }
 
-// Expansion of level `level` by virtual block `vb_id` of `nvb` blocks.
+// Expansion of level `level` by virtual block `vb_id` of `nvb` blocks. Block 0
+// first clears the counters of the ring slot two levels ahead (read at level
+// L-1, not written before level L+1). Every loop below runs the same number
+// of iterations on all lanes of a wavefront (queue-only levels use ballots).
+template <bool SPARSE>
 __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t nvb) {
   __shared__ int64_t s_lo, s_hi;
-  const int cur = level & 1;
+  __shared__ uint64_t s_acc[3][kWavesPerBlock];
+  const int cur = level % kRing;
   const int lane = lane_id();
   const uint32_t wave = threadIdx.x / kWave;
   const uint64_t gwave = (uint64_t)vb_id * kWavesPerBlock + wave;
   const uint64_t nwaves = (uint64_t)nvb * kWavesPerBlock;
+  SparseAcc acc;
+
+  if (vb_id == 0 && threadIdx.x == 0) {
+    const int r2 = (level + 2) % kRing;
+    v.ctl->qn[r2][0] = 0;
+    v.ctl->qn[r2][1] = 0;
+    v.ctl->heavy[r2] = 0;
+    v.ctl->newcnt[(level + 1) % 3] = 0;
+    v.ctl->ownedcnt[(level + 1) % 3] = 0;
+  }
 
   // Tier 2: fixed-size edge chunks of heavy vertices, one workgroup each.
   const uint64_t hv = load_relaxed64(&v.ctl->heavy[cur]);
@@ -145,16 +240,16 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
     }
     __syncthreads();
     const int64_t lo = s_lo, hi = s_hi;
-    for (int64_t e0 = lo + threadIdx.x; e0 < hi; e0 += kBlock * kUnroll) {
+    for (int64_t e0 = lo; e0 < hi; e0 += kBlock * kUnroll) {
       int32_t u[kUnroll];
       bool ok[kUnroll];
 #pragma unroll
       for (int j = 0; j < kUnroll; ++j) {
-        const int64_t e = e0 + (int64_t)j * kBlock;
+        const int64_t e = e0 + (int64_t)j * kBlock + threadIdx.x;
         ok[j] = e < hi;
         u[j] = ok[j] ? load_col(v.col, e) : 0;
       }
-      probe_batch<kUnroll>(v, u, ok);
+      probe_dispatch<SPARSE>(v, u, ok, level, acc);
     }
     __syncthreads();
   }
@@ -164,16 +259,16 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
   for (uint64_t i = gwave; i < n1; i += nwaves) {
     const int64_t li = v.q1[cur][i] - v.vb;
     const int64_t b = v.rp[li], e = v.rp[li + 1];
-    for (int64_t k0 = b + lane; k0 < e; k0 += kWave * kUnroll) {
+    for (int64_t k0 = b; k0 < e; k0 += kWave * kUnroll) {
       int32_t u[kUnroll];
       bool ok[kUnroll];
 #pragma unroll
       for (int j = 0; j < kUnroll; ++j) {
-        const int64_t k = k0 + (int64_t)j * kWave;
+        const int64_t k = k0 + (int64_t)j * kWave + lane;
         ok[j] = k < e;
         u[j] = ok[j] ? load_col(v.col, k) : 0;
       }
-      probe_batch<kUnroll>(v, u, ok);
+      probe_dispatch<SPARSE>(v, u, ok, level, acc);
     }
   }
 
@@ -190,8 +285,7 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
     const int64_t incl = wave_incl_scan(deg);
     const int64_t total = shfl64(incl, kWave - 1);
     const int64_t excl = incl - deg;
-    // Every lane runs every step (the shuffles read all lanes); edge e of the
-    // wavefront's batch belongs to the first lane k with incl[k] > e.
+    // edge e of the wavefront's batch belongs to the first lane k with incl[k] > e
     for (int64_t e0 = 0; e0 < total; e0 += kWave * kUnroll) {
       int32_t u[kUnroll];
       bool ok[kUnroll];
@@ -210,7 +304,34 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
         ok[j] = e < total;
         u[j] = ok[j] ? load_col(v.col, sk + (e - xk)) : 0;
       }
-      probe_batch<kUnroll>(v, u, ok);
+      probe_dispatch<SPARSE>(v, u, ok, level, acc);
+    }
+  }
+
+  if (SPARSE) {
+    // Level totals of the queue-only path: one atomic each per workgroup.
+    const uint64_t a = (uint64_t)wave_sum((int64_t)acc.nnew);
+    const uint64_t b = (uint64_t)wave_sum((int64_t)acc.owned);
+    const uint64_t c = (uint64_t)wave_sum((int64_t)acc.edges);
+    if (lane == 0) {
+      s_acc[0][wave] = a;
+      s_acc[1][wave] = b;
+      s_acc[2][wave] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t ta = 0, tb = 0, tc = 0;
+      for (int w = 0; w < kWavesPerBlock; ++w) {
+        ta += s_acc[0][w];
+        tb += s_acc[1][w];
+        tc += s_acc[2][w];
+      }
+      if (ta) {
+        atomic_add64(&v.ctl->newcnt[level % 3], ta);
+        atomic_add64(&v.ctl->reached, ta);
+      }
+      if (tb) atomic_add64(&v.ctl->ownedcnt[level % 3], tb);
+      if (tc) atomic_add64(&v.ctl->edges, tc);
     }
   }
 }
@@ -238,21 +359,12 @@ __device__ void merge_phase(const View &v, const MergeArgs &a, uint32_t vb_id, u
   __shared__ uint64_t s_red[2][kWavesPerBlock];
 
   const int L = a.level;
-  const int cur = L & 1, nxt = cur ^ 1;
+  const int nxt = (L + 1) % kRing;
   const int lane = lane_id();
   const int wave = threadIdx.x / kWave;
   const int32_t dnew = L + 1;
   const int cs = v.chunk_shift;
 
-  if (vb_id == 0 && threadIdx.x == 0) {
-    // The current level's queues are consumed; clear them for level L+2 and
-    // the new-vertex counters of level L+1.
-    v.ctl->qn[cur][0] = 0;
-    v.ctl->qn[cur][1] = 0;
-    v.ctl->heavy[cur] = 0;
-    v.ctl->newcnt[(L + 1) % 3] = 0;
-    v.ctl->ownedcnt[(L + 1) % 3] = 0;
-  }
   if (v.stats) {
     for (int b = threadIdx.x; b < kNumBins; b += kBlock) s_hist[b] = 0;
     __syncthreads();
@@ -428,7 +540,7 @@ __device__ void merge_phase(const View &v, const MergeArgs &a, uint32_t vb_id, u
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kBlock) k_expand(View v, int level) {
-  expand_phase(v, level, blockIdx.x, gridDim.x);
+  expand_phase<false>(v, level, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(kBlock) k_merge(View v, MergeArgs a) {
@@ -444,23 +556,37 @@ __global__ void k_clear_stats_row(View v, int level) {
 // Whole traversal in one cooperative launch: expand, barrier, merge, barrier,
 // until a level finds no new vertex. Every block runs the same number of
 // barriers; the loop also stops if a barrier tripped its spin limit.
-__global__ void __launch_bounds__(kBlock) k_persistent(View v, int max_levels) {
+__device__ __forceinline__ void persistent_body(const View &v, int max_levels) {
   const uint32_t nb = gridDim.x;
   MergeArgs a;
   a.k = 0;
   a.keep_next = 0;
   int L = 0;
   for (;; ++L) {
-    if (v.stats && L + 1 < kMaxStatLevels) {
+    // Row L+2 of the histogram is cleared a level ahead: rows L+1 are
+    // written during this level (by the merge, or by the queue-only expansion).
+    if (v.stats && L + 2 < kMaxStatLevels) {
       if (blockIdx.x == 0)
         for (int b = threadIdx.x; b < kNumBins; b += blockDim.x)
-          v.lvl_hist[(L + 1) * kNumBins + b] = 0;
+          v.lvl_hist[(L + 2) * kNumBins + b] = 0;
     }
-    expand_phase(v, L, blockIdx.x, nb);
-    grid_barrier(&v.ctl->bar, nb);
-    a.level = L;
-    merge_phase(v, a, blockIdx.x, nb);
-    grid_barrier(&v.ctl->bar, nb);
+    // Queue-only level when the frontier is small next to the bitmap sweep
+    // (every block reads the same final counters).
+    const int cur = L % kRing;
+    const uint64_t fsize = (uint64_t)load_relaxed32(&v.ctl->qn[cur][0]) +
+                           load_relaxed32(&v.ctl->qn[cur][1]) +
+                           (load_relaxed64(&v.ctl->heavy[cur]) >> kHeavyShift);
+    const bool sparse = v.sparse_div > 0 && fsize * (uint64_t)v.sparse_div < (uint64_t)v.words;
+    if (sparse) {
+      expand_phase<true>(v, L, blockIdx.x, nb);
+      grid_barrier(&v.ctl->bar, nb);
+    } else {
+      expand_phase<false>(v, L, blockIdx.x, nb);
+      grid_barrier(&v.ctl->bar, nb);
+      a.level = L;
+      merge_phase(v, a, blockIdx.x, nb);
+      grid_barrier(&v.ctl->bar, nb);
+    }
     const uint64_t nn = load_relaxed64(&v.ctl->newcnt[L % 3]);
     if (v.stats && blockIdx.x == 0 && threadIdx.x == 0 && L + 1 < kMaxStatLevels)
       v.lvl_frontier[L + 1] = (int64_t)load_relaxed64(&v.ctl->ownedcnt[L % 3]);
@@ -472,6 +598,17 @@ __global__ void __launch_bounds__(kBlock) k_persistent(View v, int max_levels) {
     v.ctl->levels = L + 1;
     if (L + 1 >= max_levels) v.ctl->err |= 2;
   }
+}
+
+// Two register budgets of the same loop: the default, and one capped at 64
+// VGPRs so 8 wavefronts fit per SIMD (more latency hiding in the expansion,
+// at the price of a few spills in the merge).
+__global__ void __launch_bounds__(kBlock) k_persistent(View v, int max_levels) {
+  persistent_body(v, max_levels);
+}
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_persistent_occ8(View v, int max_levels) {
+  persistent_body(v, max_levels);
 }
 
 // Canonical parents for the owned range: one wavefront per owned vertex takes
@@ -539,20 +676,20 @@ hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, 
   return hipGetLastError();
 }
 
-// Co-resident blocks per CU for the persistent kernel.
-int persistent_blocks_per_cu() {
+// Co-resident blocks per CU for the persistent kernel (variant 0 or 1).
+int persistent_blocks_per_cu(int variant) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent, kBlock, 0) != hipSuccess)
-    return 0;
-  return nb;
+  hipError_t e = variant ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent_occ8, kBlock, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent, kBlock, 0);
+  return e == hipSuccess ? nb : 0;
 }
 
-hipError_t launch_persistent(const View &v, int max_levels, int grid, hipStream_t s) {
+hipError_t launch_persistent(const View &v, int max_levels, int grid, int variant, hipStream_t s) {
   View vv = v;
   int ml = max_levels;
   void *args[] = {&vv, &ml};
-  return hipLaunchCooperativeKernel((const void *)k_persistent, dim3(grid), dim3(kBlock), args, 0,
-                                    s);
+  const void *fn = variant ? (const void *)k_persistent_occ8 : (const void *)k_persistent;
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlock), args, 0, s);
 }
 
 }  // namespace bfsk

@@ -90,6 +90,12 @@ void layout_relabel(const bfs_graph *g, int32_t ng, const bfs_options *o, WsLayo
     mx.tmp_col = std::max(mx.tmp_col, s.tmp_col);
     mx.temp = std::max(mx.temp, s.temp);
   }
+  // scratch distances for the autotuner (whole graphs only, like relabelling)
+  int64_t nmax_tune = 0;
+  for (int i = 0; i < ng; ++i)
+    if (g[i].v_begin == 0 && g[i].v_end == g[i].n_global && !(o && o->autotune < 0))
+      nmax_tune = std::max(nmax_tune, g[i].n_global);
+  L.tune_dist = nmax_tune > 0 ? take(sizeof(int32_t) * (size_t)nmax_tune) : 0;
   if (!any) return;
   L.rl_keys_a = take(mx.keys);
   L.rl_keys_b = take(mx.keys);
@@ -127,6 +133,12 @@ bfs_status choose_tuning(Plan *p) {
     }
     if (t.small_bin < 1 || t.wave_bin < t.small_bin || t.chunk_shift < 6)
       return p->fail(BFS_ERR_ARG, "bad tier thresholds");
+    // untuned default: the cooperative loop with the 64-VGPR budget and up to
+    // 8 blocks per CU, else launches per phase
+    t.persist_variant = p->bpc[1] > 0 ? 1 : 0;
+    const int per_cu = std::min(p->bpc[t.persist_variant], 8);
+    t.persist_grid = std::min(per_cu * p->num_cus, kBarrierGroup * kBarrierMaxGroups);
+    t.loop_mode = (p->coop && per_cu > 0) ? BFS_LOOP_PERSISTENT : BFS_LOOP_HOST;
     // cstart entries are 32-bit: total chunks must stay below 2^32.
     const int64_t m = p->graphs[i].m;
     if ((m >> t.chunk_shift) + (p->graphs[i].v_end - p->graphs[i].v_begin) >= (1ll << 32))

@@ -22,12 +22,13 @@ namespace bfsk {
 // Byte offsets of the workspace regions.
 struct WsLayout {
   size_t ctl, lvl_frontier, lvl_hist, visited, next;
-  size_t q[3][2];
-  size_t cstart[2];
+  size_t q[3][kRing];
+  size_t cstart[kRing];
   // batched multi-source state (see msbfs_core.hpp)
   // relabelled copies (per graph; 0 when the graph is not relabelled) and
   // plan-time scratch for building them
   std::vector<size_t> rl_rp, rl_col, rl_old, rl_new;
+  size_t tune_dist = 0;  // int32[n_max] scratch distances for autotuning (0: none)
   size_t rl_keys_a = 0, rl_keys_b = 0, rl_tmp_col = 0, rl_temp = 0, rl_temp_bytes = 0;
   bool ms_on = false;
   int64_t ms_ntot = 0, ms_mtot = 0;
@@ -42,6 +43,11 @@ struct Tuning {
   int32_t small_bin = 6;     // degree < 32 -> lane-group tier
   int32_t wave_bin = 13;     // degree < 4096 -> wavefront tier
   int32_t chunk_shift = 12;  // 4096-edge chunks for the workgroup tier
+  int32_t sparse_div = 4;    // queue-only level when frontier < words / 4
+  int32_t persist_variant = 0;  // 0: default registers, 1: 64-VGPR cap (8 waves/SIMD)
+  int32_t persist_grid = 0;     // blocks of the cooperative launch
+  int32_t loop_mode = 0;        // chosen level loop (BFS_LOOP_HOST or BFS_LOOP_PERSISTENT)
+  float tuned_ms = 0.f;         // best time seen by the autotuner
 };
 
 struct BatchState;  // batched / serving state (msbfs.hip)
@@ -58,7 +64,8 @@ struct bfs_plan_s {
   std::vector<bfsk::Tuning> tune;
   int num_cus = 0;
   int coop = 0;
-  int persist_grid = 0;
+  int persist_grid = 0;  // caller's grid_blocks (0: per-graph choice)
+  int bpc[2] = {0, 0};   // co-resident blocks per CU of the two persistent variants
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::string err;
 
@@ -70,6 +77,7 @@ struct bfs_plan_s {
   int32_t *cur_dist = nullptr;
   bool cur_relabel = false;  // the current traversal runs on the relabelled copy
   int32_t level = 0;
+  int32_t expanded_level = -1;  // last level bfs_expand ran for
   int32_t persistent_levels = 0;
   int64_t last_level_new = 0;
   float last_ms = 0.f;
@@ -98,6 +106,7 @@ void layout_single(const bfs_graph *g, int32_t ng, WsLayout &L, size_t &off);
 void layout_relabel(const bfs_graph *g, int32_t ng, const bfs_options *o, WsLayout &L, size_t &off);
 bool relabel_wanted(const bfs_graph &g, const bfs_options *o);
 bfs_status relabel_graphs(Plan *p);
+bfs_status autotune_graphs(Plan *p);
 void layout_batch(const bfs_graph *g, int32_t ng, const bfs_options *o, WsLayout &L, size_t &off);
 bfs_status validate_graphs(Plan *p);
 bfs_status choose_tuning(Plan *p);
