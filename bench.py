@@ -66,6 +66,33 @@ def host_facts():
     return {"nproc": os.cpu_count(), "cpu": cpu, "mem_gb": mem_gb}
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("bfs_kernels.hip", "bfs_core.hpp", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_2103_13577_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, per_launch_bytes):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size),
+    or None when the summary was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_rmat24.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return {"bytes_per_launch": k["hbm_bytes_per_launch"],
+            "vs_algorithmic": round(k["hbm_bytes_per_launch"] / max(per_launch_bytes, 1.0), 3),
+            "source": "profiles/traffic_rmat24.json"}
+
+
 def cpu_baseline_single(g, sources, budget_s=20.0):
     """Times the CPU oracle (single-threaded FIFO BFS) on a bounded sample of
     the same sources: whole traversals until about budget_s of CPU work."""
@@ -96,7 +123,8 @@ def run_single(args, name, scale, ef):
     dev = torch.device("cuda:0")
     dg = pkg.DeviceGraph.from_csr(g, dev)
     plan = pkg.Plan([dg], loop_mode=args.loop_mode, grid_blocks=args.grid_blocks,
-                    small_bin=args.small_bin, wave_bin=args.wave_bin, chunk_edges=args.chunk_edges)
+                    small_bin=args.small_bin, wave_bin=args.wave_bin, chunk_edges=args.chunk_edges,
+                    relabel=args.relabel, autotune=args.autotune)
     srcs = gg.pick_sources(g, args.warmup + args.steps, seed=sseed)
     dist = torch.empty(g.n, dtype=torch.int32, device=dev)
     for s in srcs[:args.warmup]:
@@ -115,11 +143,28 @@ def run_single(args, name, scale, ef):
     reached = np.array([s.reached for s in stats], dtype=np.float64)
     rates = edges / (ms * 1e-3) / 1e9
     hmean = metrics.harmonic_mean(rates)
-    # roofline of the dominant kernel (the level loop): algorithmic bytes per
-    # launch = 4 B per scanned column index + 16 B of row offsets per frontier
-    # vertex + 4 B per distance written, over the launch's own duration
-    loop_bytes = 4 * edges + 16 * reached + 4 * reached
-    achieved = float(np.mean(loop_bytes) / (np.mean(loop_ms) * 1e-3) / 1e9)
+    tuning = plan.tuning(0)
+    if tuning["loop_mode"] == 1:
+        # host-driven loop: the dominant kernel is the expansion; per
+        # traversal it reads every scanned column index (4 B) and two int64
+        # row offsets per frontier vertex (16 B); its launches are timed with
+        # HIP events on the plan's stream
+        kname = "k_expand"
+        exp_ms = np.array([s.expand_ms for s in stats])
+        launches = np.array([max(s.expand_launches, 1) for s in stats])
+        k_bytes = 4 * edges + 16 * reached
+        achieved = float(np.sum(k_bytes) / (np.sum(exp_ms) * 1e-3) / 1e9)
+        per_launch_bytes = float(np.sum(k_bytes) / np.sum(launches))
+        avg_launch_ms = float(np.sum(exp_ms) / np.sum(launches))
+    else:
+        # device-resident loop: one launch per traversal, which also writes
+        # each reached vertex's distance (4 B)
+        kname = "k_persistent_occ8" if tuning["persist_variant"] == 1 else "k_persistent"
+        k_bytes = 4 * edges + 16 * reached + 4 * reached
+        achieved = float(np.mean(k_bytes) / (np.mean(loop_ms) * 1e-3) / 1e9)
+        per_launch_bytes = float(np.mean(k_bytes))
+        avg_launch_ms = float(np.mean(loop_ms))
+    traffic = measured_traffic(kname, per_launch_bytes)
     whole_bytes = np.array([metrics.bytes_single_source(e, r, g.n) for e, r in zip(edges, reached)])
     out = {
         "metric": "GTEPS (1 MI355X, all edges) + batched queries/sec with p50/p99 latency",
@@ -141,9 +186,9 @@ def run_single(args, name, scale, ef):
                    "plan": plan.tuning(0)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "k_persistent",
-                     "bytes_per_launch": int(np.mean(loop_bytes)),
-                     "avg_launch_ms": round(float(np.mean(loop_ms)), 4)},
+                     "traffic": traffic, "kernel": kname,
+                     "bytes_per_launch": int(per_launch_bytes),
+                     "avg_launch_ms": round(avg_launch_ms, 4)},
         "detail": {
             "gteps_trimmed_mean_time": round(metrics.gteps(np.mean(edges), metrics.trimmed_mean(ms) * 1e-3), 3),
             "gteps_whole_graph_convention": round(metrics.harmonic_mean(g.m / (ms * 1e-3) / 1e9), 3),
@@ -518,6 +563,51 @@ def run_share29(args):
     return out
 
 
+def summarize_pmc(args):
+    """Writes profiles/traffic_rmat24.json from rocprofv3 --pmc runs: the mean
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of each kernel, scaled by what
+    the same counters read for a plain device copy of known size."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(d, counter):
+        tot, n = defaultdict(float), defaultdict(set)
+        with open(os.path.join(d, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                k = r["Kernel_Name"].split("(")[0].split("::")[-1]
+                tot[k] += float(r["Counter_Value"])
+                n[k].add(r["Dispatch_Id"])
+        return {k: tot[k] / len(n[k]) for k in tot}, {k: len(n[k]) for k in n}
+
+    fd, wd, cfd, cwd = args.summarize_pmc
+    fetch, nf = per_kernel(fd, "FETCH_SIZE")
+    write, _ = per_kernel(wd, "WRITE_SIZE")
+    cf, _ = per_kernel(cfd, "FETCH_SIZE")
+    cw, _ = per_kernel(cwd, "WRITE_SIZE")
+    copy_kib = args.copy_bytes / 1024.0
+    ck = [k for k in cf if "copy" in k.lower()][0]
+    fscale, wscale = copy_kib / cf[ck], copy_kib / cw[ck]
+    out = {"workload": "R-MAT scale 24 edge factor 16, host-driven level loop",
+           "kernel_source_hash": kernel_source_hash(),
+           "copy_probe": {"bytes": args.copy_bytes, "fetch_kib": cf[ck], "write_kib": cw[ck],
+                          "fetch_scale": fscale, "write_scale": wscale},
+           "kernels": {}}
+    for k in fetch:
+        if k not in ("k_expand", "k_merge", "k_reset"):
+            continue
+        fb = fetch[k] * fscale * 1024
+        wb = write.get(k, 0.0) * wscale * 1024
+        out["kernels"][k] = {"dispatches": nf[k], "fetch_bytes_per_launch": int(fb),
+                             "write_bytes_per_launch": int(wb),
+                             "hbm_bytes_per_launch": int(fb + wb)}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "traffic_rmat24.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def copy_probe(nbytes):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -541,6 +631,8 @@ def main():
     ap.add_argument("--small-bin", type=int, default=0)
     ap.add_argument("--wave-bin", type=int, default=0)
     ap.add_argument("--chunk-edges", type=int, default=0)
+    ap.add_argument("--relabel", type=int, default=0, help="0 auto, 1 on, -1 off")
+    ap.add_argument("--autotune", type=int, default=0, help="0 auto, 1 on, -1 off")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=int, default=0)
@@ -549,6 +641,9 @@ def main():
     ap.add_argument("--serve-buffers", type=int, default=96)
     ap.add_argument("--serve-sample", type=int, default=200)
     ap.add_argument("--share-scale", type=int, default=29)
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                         "COPY_WRITE_DIR"))
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
@@ -557,6 +652,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(args)
         return
     if args.workload == "rmat24":
         out = run_single(args, "rmat24", 24, 16)

@@ -115,6 +115,10 @@ typedef struct {
   float ms;              /* device time of the whole traversal, reset included (HIP events) */
   float loop_ms;         /* device time of the level loop alone (the persistent launch, or
                             first expansion to last merge when host-driven) */
+  float expand_ms;       /* host-driven loop: summed device time of the expansion launches
+                            of the first 64 levels (0 for the persistent loop) */
+  float merge_ms;        /* the same for the merge launches */
+  int32_t expand_launches; /* launches summed in expand_ms */
 } bfs_stats;
 
 #define BFS_MAX_LEVEL_STATS 4096

@@ -49,7 +49,8 @@ class bfs_options(ctypes.Structure):
 class bfs_stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("reached", ctypes.c_int64),
                 ("edges_scanned", ctypes.c_int64), ("ms", ctypes.c_float),
-                ("loop_ms", ctypes.c_float)]
+                ("loop_ms", ctypes.c_float), ("expand_ms", ctypes.c_float),
+                ("merge_ms", ctypes.c_float), ("expand_launches", ctypes.c_int32)]
 
 
 class bfs_tuning(ctypes.Structure):
@@ -162,6 +163,9 @@ class Stats:
     edges_scanned: int
     ms: float
     loop_ms: float
+    expand_ms: float = 0.0
+    merge_ms: float = 0.0
+    expand_launches: int = 0
 
 
 class Plan:
@@ -253,7 +257,7 @@ class Plan:
         st = bfs_stats()
         self._check(lib().bfs_run(self.h, graph, int(source), dist.data_ptr(),
                                   par.data_ptr() if par is not None else None, ctypes.byref(st)))
-        return dist, par, Stats(st.levels, st.reached, st.edges_scanned, st.ms, st.loop_ms)
+        return dist, par, Stats(st.levels, st.reached, st.edges_scanned, st.ms, st.loop_ms, st.expand_ms, st.merge_ms, st.expand_launches)
 
     def begin(self, graph: int, source: int, dist):
         self._check(lib().bfs_begin(self.h, graph, int(source), dist.data_ptr()))
@@ -279,7 +283,7 @@ class Plan:
         st = bfs_stats()
         self._check(lib().bfs_finish(self.h, parent.data_ptr() if parent is not None else None,
                                      ctypes.byref(st)))
-        return Stats(st.levels, st.reached, st.edges_scanned, st.ms, st.loop_ms)
+        return Stats(st.levels, st.reached, st.edges_scanned, st.ms, st.loop_ms, st.expand_ms, st.merge_ms, st.expand_launches)
 
     def tuning(self, graph: int = 0) -> dict:
         """Settings the plan uses for one graph (after autotuning)."""

@@ -98,7 +98,7 @@ View bfs_plan_s::view(int32_t gi, int32_t *dist) const {
   return v;
 }
 
-int bfs_plan_s::wide_grid() const { return num_cus * 8; }
+int bfs_plan_s::wide_grid() const { return num_cus * std::max(bpc_expand, 1); }
 
 int bfs_plan_s::merge_grid(int64_t words) const {
   int64_t g = (words + kBlock - 1) / kBlock;
@@ -188,6 +188,7 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
   p->coop = prop.cooperativeLaunch;
   p->bpc[0] = persistent_blocks_per_cu(0);
   p->bpc[1] = persistent_blocks_per_cu(1);
+  p->bpc_expand = expand_blocks_per_cu();
   p->persist_grid = o->grid_blocks;  // 0: chosen per graph
   if (o->grid_blocks > kBarrierGroup * kBarrierMaxGroups) {
     g_create_error = "grid_blocks above the grid barrier's limit of 2048";
@@ -201,6 +202,13 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
       return BFS_ERR_HIP;
     }
   }
+  for (auto &row : p->lev)
+    for (auto &ev : row)
+      if (hipEventCreate(&ev) != hipSuccess) {
+        g_create_error = "hipEventCreate failed";
+        delete p;
+        return BFS_ERR_HIP;
+      }
   st = validate_graphs(p);
   if (st) { g_create_error = p->err; delete p; return st; }
   st = choose_tuning(p);
@@ -271,8 +279,11 @@ bfs_status bfs_expand(bfs_plan_t p, const uint64_t **local_next) {
     if (e != hipSuccess) return p->hip_fail(e, "stats launch");
   }
   if (p->expanded_level == p->level) return p->fail(BFS_ERR_STATE, "level already expanded");
+  const bool timed = p->time_levels && p->level < Plan::kTimedLevels;
+  if (timed) (void)hipEventRecord(p->lev[p->level][0], p->stream);
   hipError_t e = launch_expand(v, p->level, p->wide_grid(), p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "expand launch");
+  if (timed) (void)hipEventRecord(p->lev[p->level][1], p->stream);
   p->expanded_level = p->level;
   if (local_next) *local_next = v.next;
   return BFS_OK;
@@ -299,6 +310,8 @@ bfs_status bfs_merge_frontier(bfs_plan_t p, const uint64_t *const *incoming, int
     hipError_t e = launch_merge(v, a, p->merge_grid(v.words), p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "merge launch");
   } while (done < k);
+  if (!keep_next && p->time_levels && p->level < Plan::kTimedLevels)
+    (void)hipEventRecord(p->lev[p->level][2], p->stream);
   if (global_new || owned_new || !keep_next) {
     Ctl c;
     bfs_status st = p->read_ctl(c);
@@ -333,6 +346,9 @@ bfs_status bfs_finish(bfs_plan_t p, int32_t *parent, bfs_stats *st) {
     st->edges_scanned = (int64_t)c.edges;
     st->ms = p->last_ms;
     st->loop_ms = p->last_loop_ms;
+    st->expand_ms = p->last_expand_ms;
+    st->merge_ms = p->last_merge_ms;
+    st->expand_launches = p->last_expand_launches;
   }
   return BFS_OK;
 }
@@ -346,6 +362,8 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   p->persistent_levels = 0;
   p->last_ms = 0.f;
   p->last_loop_ms = 0.f;
+  p->last_expand_ms = p->last_merge_ms = 0.f;
+  p->last_expand_launches = 0;
   e = hipEventRecord(ev0, p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
   s = begin_impl(p, graph, source, dist, p->opt.exchange == nullptr);
@@ -385,24 +403,32 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   } else {
     e = hipEventRecord(p->ev[2], p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
+    p->time_levels = true;
     for (;;) {
       const uint64_t *local_next = nullptr;
       s = bfs_expand(p, &local_next);
-      if (s) return s;
+      if (s) { p->time_levels = false; return s; }
       const uint64_t *const *inc = nullptr;
       int32_t k = 0;
       if (p->opt.exchange) {
         e = hipStreamSynchronize(p->stream);
         if (e != hipSuccess) return p->hip_fail(e, "hipStreamSynchronize");
         int32_t rc = p->opt.exchange(p->opt.exchange_ctx, p->level, local_next, &inc, &k);
-        if (rc != 0) return p->fail(BFS_ERR_EXCHANGE, "exchange callback returned " + std::to_string(rc));
-        if (k < 0 || (k > 0 && !inc)) return p->fail(BFS_ERR_EXCHANGE, "exchange callback gave a bad list");
+        if (rc != 0) {
+        p->time_levels = false;
+        return p->fail(BFS_ERR_EXCHANGE, "exchange callback returned " + std::to_string(rc));
+      }
+        if (k < 0 || (k > 0 && !inc)) {
+        p->time_levels = false;
+        return p->fail(BFS_ERR_EXCHANGE, "exchange callback gave a bad list");
+      }
       }
       int64_t gnew = 0;
       s = bfs_merge_frontier(p, inc, k, 0, &gnew, nullptr);
-      if (s) return s;
+      if (s) { p->time_levels = false; return s; }
       if (gnew == 0) break;
     }
+    p->time_levels = false;
     e = hipEventRecord(ev1, p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
   }
@@ -413,6 +439,17 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   if (hipEventElapsedTime(&lms, p->ev[2], ev1) != hipSuccess) lms = -1.f;
   p->last_ms = ms;
   p->last_loop_ms = lms;
+  p->last_expand_ms = p->last_merge_ms = 0.f;
+  p->last_expand_launches = 0;
+  if (host_loop) {
+    const int nl = std::min(p->level, Plan::kTimedLevels);
+    for (int L = 0; L < nl; ++L) {
+      float a = 0.f, b = 0.f;
+      if (hipEventElapsedTime(&a, p->lev[L][0], p->lev[L][1]) == hipSuccess) p->last_expand_ms += a;
+      if (hipEventElapsedTime(&b, p->lev[L][1], p->lev[L][2]) == hipSuccess) p->last_merge_ms += b;
+    }
+    p->last_expand_launches = nl;
+  }
   return bfs_finish(p, parent, st);
 }
 

@@ -91,5 +91,6 @@ hipError_t launch_clear_stats_row(const View &v, int level, hipStream_t s);
 hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, hipStream_t s);
 hipError_t launch_persistent(const View &v, int max_levels, int grid, int variant, hipStream_t s);
 int persistent_blocks_per_cu(int variant);
+int expand_blocks_per_cu();
 
 }  // namespace bfsk

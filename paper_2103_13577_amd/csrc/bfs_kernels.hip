@@ -181,13 +181,14 @@ __device__ __forceinline__ void probe_batch_sparse(const View &v, const int32_t 
   }
 }
 
-constexpr int kUnroll = 4;  // edges per lane in flight
+constexpr int kUnroll = 4;       // edges per lane in flight (wavefront / workgroup tiers)
+constexpr int kUnrollSmall = 8;  // edges per lane in flight (lane-group tier)
 
-template <bool SPARSE>
-__device__ __forceinline__ void probe_dispatch(const View &v, const int32_t (&u)[kUnroll],
-                                               const bool (&ok)[kUnroll], int L, SparseAcc &acc) {
-  if (SPARSE) probe_batch_sparse<kUnroll>(v, u, ok, L, acc);
-  else probe_batch<kUnroll>(v, u, ok);
+template <bool SPARSE, int K>
+__device__ __forceinline__ void probe_dispatch(const View &v, const int32_t (&u)[K],
+                                               const bool (&ok)[K], int L, SparseAcc &acc) {
+  if (SPARSE) probe_batch_sparse<K>(v, u, ok, L, acc);
+  else probe_batch<K>(v, u, ok);
 }
 
 // Largest s in [0, n) with a[s] <= key (a ascending, a[0] == 0 <= key).
@@ -249,7 +250,7 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
         ok[j] = e < hi;
         u[j] = ok[j] ? load_col(v.col, e) : 0;
       }
-      probe_dispatch<SPARSE>(v, u, ok, level, acc);
+      probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc);
     }
     __syncthreads();
   }
@@ -268,7 +269,7 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
         ok[j] = k < e;
         u[j] = ok[j] ? load_col(v.col, k) : 0;
       }
-      probe_dispatch<SPARSE>(v, u, ok, level, acc);
+      probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc);
     }
   }
 
@@ -286,11 +287,11 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
     const int64_t total = shfl64(incl, kWave - 1);
     const int64_t excl = incl - deg;
     // edge e of the wavefront's batch belongs to the first lane k with incl[k] > e
-    for (int64_t e0 = 0; e0 < total; e0 += kWave * kUnroll) {
-      int32_t u[kUnroll];
-      bool ok[kUnroll];
+    for (int64_t e0 = 0; e0 < total; e0 += kWave * kUnrollSmall) {
+      int32_t u[kUnrollSmall];
+      bool ok[kUnrollSmall];
 #pragma unroll
-      for (int j = 0; j < kUnroll; ++j) {
+      for (int j = 0; j < kUnrollSmall; ++j) {
         const int64_t e = e0 + (int64_t)j * kWave + lane;
         int k = 0;
 #pragma unroll
@@ -304,7 +305,7 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
         ok[j] = e < total;
         u[j] = ok[j] ? load_col(v.col, sk + (e - xk)) : 0;
       }
-      probe_dispatch<SPARSE>(v, u, ok, level, acc);
+      probe_dispatch<SPARSE, kUnrollSmall>(v, u, ok, level, acc);
     }
   }
 
@@ -394,33 +395,57 @@ __device__ void merge_phase(const View &v, const MergeArgs &a, uint32_t vb_id, u
     my_new += (uint64_t)__popcll(nw);
 
     // Pass 1: distances of new vertices; degree tier of owned new vertices.
+    // Words are taken four at a time (lanes = the 64 bits of a word) so the
+    // row-offset loads of four words are in flight together.
     uint64_t t1m = 0, t2m = 0;
     uint64_t chunks = 0;  // wave-uniform
     uint64_t act = ballot(nw != 0);
     while (act) {
-      const int j = __ffsll((unsigned long long)act) - 1;
-      act &= act - 1;
-      const uint64_t wj = readlane64(nw, j);
-      const uint64_t oj = readlane64(om, j);
-      const int64_t vtx = (wbase + j) * 64 + lane;
-      if ((wj >> lane) & 1ull) v.dist[v.old_id ? (int64_t)v.old_id[vtx] : vtx] = dnew;
-      int t = 0;
-      int64_t deg = 0;
-      const bool own = (oj >> lane) & 1ull;
-      if (own) {
-        const int64_t li = vtx - v.vb;
-        deg = v.rp[li + 1] - v.rp[li];
-        const int b = degree_bin(deg);
-        t = tier_of_bin(b, v.small_bin, v.wave_bin);
-        my_edges += (uint64_t)deg;
-        if (v.stats) atomicAdd(&s_hist[b], 1u);
+      constexpr int kW = 4;
+      int js[kW];
+      int cnt = 0;
+#pragma unroll
+      for (int q = 0; q < kW; ++q) {
+        js[q] = act ? __ffsll((unsigned long long)act) - 1 : 0;
+        if (act) { act &= act - 1; ++cnt; }
       }
-      const uint64_t m1 = ballot(own && t == 1);
-      const uint64_t m2 = ballot(own && t == 2);
-      if (lane == j) { t1m = m1; t2m = m2; }
-      if (m2) {
-        const uint64_t nc = (own && t == 2) ? (uint64_t)((deg + (1ll << cs) - 1) >> cs) : 0ull;
-        chunks += (uint64_t)wave_sum((int64_t)nc);
+      bool own[kW];
+      int64_t r0[kW], r1[kW];
+#pragma unroll
+      for (int q = 0; q < kW; ++q) {
+        own[q] = false;
+        r0[q] = r1[q] = 0;
+        if (q < cnt) {
+          const uint64_t wj = readlane64(nw, js[q]);
+          const uint64_t oj = readlane64(om, js[q]);
+          const int64_t vtx = (wbase + js[q]) * 64 + lane;
+          if ((wj >> lane) & 1ull) v.dist[v.old_id ? (int64_t)v.old_id[vtx] : vtx] = dnew;
+          own[q] = (oj >> lane) & 1ull;
+          if (own[q]) {
+            const int64_t li = vtx - v.vb;
+            r0[q] = v.rp[li];
+            r1[q] = v.rp[li + 1];
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kW; ++q) {
+        if (q >= cnt) break;
+        int t = 0;
+        const int64_t deg = r1[q] - r0[q];
+        if (own[q]) {
+          const int b = degree_bin(deg);
+          t = tier_of_bin(b, v.small_bin, v.wave_bin);
+          my_edges += (uint64_t)deg;
+          if (v.stats) atomicAdd(&s_hist[b], 1u);
+        }
+        const uint64_t m1 = ballot(own[q] && t == 1);
+        const uint64_t m2 = ballot(own[q] && t == 2);
+        if (lane == js[q]) { t1m = m1; t2m = m2; }
+        if (m2) {
+          const uint64_t nc = (own[q] && t == 2) ? (uint64_t)((deg + (1ll << cs) - 1) >> cs) : 0ull;
+          chunks += (uint64_t)wave_sum((int64_t)nc);
+        }
       }
     }
     const uint32_t c0 = wave_sum_u32((uint32_t)__popcll(om & ~t1m & ~t2m));
@@ -674,6 +699,12 @@ hipError_t launch_clear_stats_row(const View &v, int level, hipStream_t s) {
 hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_parent, dim3(grid), dim3(kBlock), 0, s, v, parent, src);
   return hipGetLastError();
+}
+
+// Co-resident blocks per CU of the per-phase expansion kernel.
+int expand_blocks_per_cu() {
+  int nb = 0;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_expand, kBlock, 0) == hipSuccess ? nb : 0;
 }
 
 // Co-resident blocks per CU for the persistent kernel (variant 0 or 1).

@@ -66,7 +66,11 @@ struct bfs_plan_s {
   int coop = 0;
   int persist_grid = 0;  // caller's grid_blocks (0: per-graph choice)
   int bpc[2] = {0, 0};   // co-resident blocks per CU of the two persistent variants
+  int bpc_expand = 0;    // co-resident blocks per CU of the per-phase expansion
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  static constexpr int kTimedLevels = 64;
+  hipEvent_t lev[kTimedLevels][3] = {};  // per level: before expand, after expand, after merge
+  bool time_levels = false;              // set while bfs_run drives the host loop
   std::string err;
 
   // single-source traversal state
@@ -82,6 +86,8 @@ struct bfs_plan_s {
   int64_t last_level_new = 0;
   float last_ms = 0.f;
   float last_loop_ms = 0.f;
+  float last_expand_ms = 0.f, last_merge_ms = 0.f;
+  int32_t last_expand_launches = 0;
   std::vector<int64_t> level_frontier;
 
   bfsk::BatchState *batch = nullptr;
@@ -96,6 +102,9 @@ struct bfs_plan_s {
   ~bfs_plan_s() {
     for (auto &e : ev)
       if (e) (void)hipEventDestroy(e);
+    for (auto &row : lev)
+      for (auto &e : row)
+        if (e) (void)hipEventDestroy(e);
   }
 };
 
