@@ -83,6 +83,7 @@ typedef int32_t (*bfs_exchange_fn)(void *ctx, int32_t level, const uint64_t *loc
 #define BFS_LOOP_AUTO 0       /* device-resident loop when no exchange callback */
 #define BFS_LOOP_HOST 1       /* one launch per phase, host reads the new count */
 #define BFS_LOOP_PERSISTENT 2 /* whole traversal in one cooperative launch */
+#define BFS_LOOP_GRAPH 3      /* a captured hipGraph of 8 level steps, replayed until done */
 
 typedef struct {
   void *hip_stream;        /* hipStream_t; NULL = the null stream */
@@ -149,7 +150,7 @@ const char *bfs_last_error(bfs_plan_t p);
 
 /* Settings the plan uses for one graph (after autotuning). */
 typedef struct {
-  int32_t loop_mode;        /* BFS_LOOP_HOST or BFS_LOOP_PERSISTENT */
+  int32_t loop_mode;        /* BFS_LOOP_HOST, BFS_LOOP_PERSISTENT or BFS_LOOP_GRAPH */
   int32_t persist_variant;  /* 0: default registers, 1: 64-VGPR budget */
   int32_t grid_blocks;      /* blocks of the persistent launch */
   int32_t small_bin;

@@ -93,8 +93,10 @@ bfs_status autotune_graphs(Plan *p) {
       Tuning h = t;
       h.loop_mode = BFS_LOOP_HOST;
       loops.push_back(h);
+      h.loop_mode = BFS_LOOP_GRAPH;
+      loops.push_back(h);
     }
-    if (p->coop && p->opt.loop_mode != BFS_LOOP_HOST) {
+    if (p->coop && (p->opt.loop_mode == BFS_LOOP_AUTO || p->opt.loop_mode == BFS_LOOP_PERSISTENT)) {
       for (int var = 0; var < 2; ++var) {
         const int bpc = p->bpc[var];
         for (int per_cu : {bpc, bpc / 2}) {

@@ -209,6 +209,13 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
         delete p;
         return BFS_ERR_HIP;
       }
+  if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    g_create_error = "hipStreamCreate failed";
+    delete p;
+    return BFS_ERR_HIP;
+  }
+  p->gexec.assign(ngraphs, nullptr);
+  p->gexec_tune.assign(ngraphs, Tuning{});
   st = validate_graphs(p);
   if (st) { g_create_error = p->err; delete p; return st; }
   st = choose_tuning(p);
@@ -353,6 +360,50 @@ bfs_status bfs_finish(bfs_plan_t p, int32_t *parent, bfs_stats *st) {
   return BFS_OK;
 }
 
+namespace {
+
+bool same_tuning(const Tuning &a, const Tuning &b) {
+  return a.small_bin == b.small_bin && a.wave_bin == b.wave_bin && a.chunk_shift == b.chunk_shift &&
+         a.sparse_div == b.sparse_div;
+}
+
+// The captured graph of kGraphLevels level steps for graph gi (captured on
+// first use, and again when the tier settings changed).
+bfs_status graph_exec(bfs_plan_t p, int32_t gi, hipGraphExec_t &out) {
+  if (p->gexec[gi] && same_tuning(p->gexec_tune[gi], p->tune[gi])) {
+    out = p->gexec[gi];
+    return BFS_OK;
+  }
+  if (p->gexec[gi]) {
+    (void)hipGraphExecDestroy(p->gexec[gi]);
+    p->gexec[gi] = nullptr;
+  }
+  View v = p->view(gi, nullptr);  // the kernels take the distance array from the control block
+  const int max_levels = (int)std::min<int64_t>(p->graphs[gi].n_global + 1, 1ll << 30);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return p->hip_fail(e, "hipStreamBeginCapture");
+  hipError_t el = enqueue_graph_levels(v, Plan::kGraphLevels, max_levels, p->wide_grid(),
+                                       p->merge_grid(v.words), p->cap_stream);
+  e = hipStreamEndCapture(p->cap_stream, &g);
+  if (el != hipSuccess) e = el;
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return p->hip_fail(e, "level graph capture");
+  }
+  e = hipGraphInstantiate(&p->gexec[gi], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    p->gexec[gi] = nullptr;
+    return p->hip_fail(e, "hipGraphInstantiate");
+  }
+  p->gexec_tune[gi] = p->tune[gi];
+  out = p->gexec[gi];
+  return BFS_OK;
+}
+
+}  // namespace
+
 bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, int32_t *parent,
                    bfs_stats *st) {
   if (!p) return BFS_ERR_ARG;
@@ -383,8 +434,29 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
       mode = BFS_LOOP_HOST;
     }
   }
-  const bool host_loop = mode != BFS_LOOP_PERSISTENT;
-  if (!host_loop) {
+  const bool host_loop = mode == BFS_LOOP_HOST;
+  if (mode == BFS_LOOP_GRAPH) {
+    hipGraphExec_t ge = nullptr;
+    s = graph_exec(p, graph, ge);
+    if (s) return s;
+    e = hipEventRecord(p->ev[2], p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
+    const int64_t max_launches = g.n_global / Plan::kGraphLevels + 2;
+    Ctl c;
+    for (int64_t i = 0;; ++i) {
+      e = hipGraphLaunch(ge, p->stream);
+      if (e != hipSuccess) return p->hip_fail(e, "hipGraphLaunch");
+      s = p->read_ctl(c);
+      if (s) return s;
+      if (c.gdone) break;
+      if (i + 1 >= max_launches) return p->fail(BFS_ERR_DEVICE, "level limit exceeded");
+    }
+    e = hipEventRecord(ev1, p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
+    if (c.err) return p->fail(BFS_ERR_DEVICE, "level limit exceeded");
+    p->persistent_levels = c.levels;
+    p->level = c.levels;
+  } else if (!host_loop) {
     View v = p->view(graph, dist);
     const int max_levels = (int)std::min<int64_t>(g.n_global + 1, 1ll << 30);
     e = hipEventRecord(p->ev[2], p->stream);

@@ -29,7 +29,10 @@ struct Ctl {
   uint64_t reached;       // vertices with a finite distance
   int32_t levels;         // persistent loop: number of nonempty levels
   int32_t err;            // device-side error flags
-  uint64_t pad[3];
+  int32_t glevel;         // graph-launched loop: level the next captured step runs
+  int32_t gdone;          // graph-launched loop: traversal finished
+  int32_t *gdist;         // graph-launched loop: caller's distance array
+  uint64_t pad[1];
 };
 
 // Kernel view of a plan's workspace for one graph.
@@ -90,6 +93,10 @@ hipError_t launch_merge(const View &v, const MergeArgs &a, int grid, hipStream_t
 hipError_t launch_clear_stats_row(const View &v, int level, hipStream_t s);
 hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, hipStream_t s);
 hipError_t launch_persistent(const View &v, int max_levels, int grid, int variant, hipStream_t s);
+// Enqueues `levels` graph-launched level steps (expand, merge, advance) on s;
+// used while capturing a hipGraph.
+hipError_t enqueue_graph_levels(const View &v, int levels, int max_levels, int expand_grid,
+                                int merge_grid, hipStream_t s);
 int persistent_blocks_per_cu(int variant);
 int expand_blocks_per_cu();
 

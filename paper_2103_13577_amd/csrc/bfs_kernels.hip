@@ -55,6 +55,9 @@ __global__ void __launch_bounds__(kBlock) k_reset(View v, int64_t src_caller) {
     c->reached = 1;
     c->levels = 0;
     c->err = 0;
+    c->glevel = 0;
+    c->gdone = 0;
+    c->gdist = v.dist;
     const bool owned = src >= v.vb && src < v.ve;
     int64_t deg = 0;
     if (owned) {
@@ -570,6 +573,70 @@ __global__ void __launch_bounds__(kBlock) k_expand(View v, int level) {
 
 __global__ void __launch_bounds__(kBlock) k_merge(View v, MergeArgs a) {
   merge_phase(v, a, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// graph-launched level loop: the same phases as launches whose level comes
+// from the control block, so a fixed sequence can be captured in a hipGraph
+// and replayed until the traversal is done
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool level_is_sparse(const View &v, int L) {
+  const int cur = L % kRing;
+  const uint64_t fsize = (uint64_t)load_relaxed32(&v.ctl->qn[cur][0]) +
+                         load_relaxed32(&v.ctl->qn[cur][1]) +
+                         (load_relaxed64(&v.ctl->heavy[cur]) >> kHeavyShift);
+  return v.sparse_div > 0 && fsize * (uint64_t)v.sparse_div < (uint64_t)v.words;
+}
+
+__global__ void __launch_bounds__(kBlock) k_expand_g(View v) {
+  if (load_relaxed_i32(&v.ctl->gdone)) return;
+  const int L = load_relaxed_i32(&v.ctl->glevel);
+  View w = v;
+  w.dist = v.ctl->gdist;
+  if (level_is_sparse(w, L)) expand_phase<true>(w, L, blockIdx.x, gridDim.x);
+  else expand_phase<false>(w, L, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_merge_g(View v) {
+  if (load_relaxed_i32(&v.ctl->gdone)) return;
+  const int L = load_relaxed_i32(&v.ctl->glevel);
+  if (level_is_sparse(v, L)) return;  // a queue-only level has nothing to merge
+  View w = v;
+  w.dist = v.ctl->gdist;
+  MergeArgs a{};
+  a.k = 0;
+  a.keep_next = 0;
+  a.level = L;
+  merge_phase(w, a, blockIdx.x, gridDim.x);
+}
+
+// One thread: termination test and level advance; clears the histogram row
+// written two levels ahead.
+__global__ void k_advance_g(View v, int max_levels) {
+  if (threadIdx.x != 0 || load_relaxed_i32(&v.ctl->gdone)) return;
+  const int L = v.ctl->glevel;
+  const uint64_t nn = v.ctl->newcnt[L % 3];
+  if (v.stats && L + 1 < kMaxStatLevels) v.lvl_frontier[L + 1] = (int64_t)v.ctl->ownedcnt[L % 3];
+  if (v.stats && L + 2 < kMaxStatLevels)
+    for (int b = 0; b < kNumBins; ++b) v.lvl_hist[(L + 2) * kNumBins + b] = 0;
+  if (nn == 0 || L + 1 >= max_levels) {
+    v.ctl->gdone = 1;
+    v.ctl->levels = L + 1;
+    if (nn != 0) v.ctl->err |= 2;
+  } else {
+    v.ctl->glevel = L + 1;
+  }
+}
+
+hipError_t enqueue_graph_levels(const View &v, int levels, int max_levels, int expand_grid,
+                                int merge_grid, hipStream_t s) {
+  for (int i = 0; i < levels; ++i) {
+    hipLaunchKernelGGL(k_expand_g, dim3(expand_grid), dim3(kBlock), 0, s, v);
+    hipLaunchKernelGGL(k_merge_g, dim3(merge_grid), dim3(kBlock), 0, s, v);
+    hipLaunchKernelGGL(k_advance_g, dim3(1), dim3(64), 0, s, v, max_levels);
+  }
+  return hipGetLastError();
 }
 
 // Clears the stats row of a level before its merge (host-driven loop).

@@ -90,6 +90,13 @@ struct bfs_plan_s {
   int32_t last_expand_launches = 0;
   std::vector<int64_t> level_frontier;
 
+  // captured level-step graphs, one per graph index, with the settings they
+  // were captured with
+  static constexpr int kGraphLevels = 8;
+  hipStream_t cap_stream = nullptr;
+  std::vector<hipGraphExec_t> gexec;
+  std::vector<bfsk::Tuning> gexec_tune;
+
   bfsk::BatchState *batch = nullptr;
 
   bfs_status fail(bfs_status st, const std::string &msg);
@@ -105,6 +112,9 @@ struct bfs_plan_s {
     for (auto &row : lev)
       for (auto &e : row)
         if (e) (void)hipEventDestroy(e);
+    for (auto &g : gexec)
+      if (g) (void)hipGraphExecDestroy(g);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
 

@@ -46,7 +46,10 @@ MODES = [dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST),
          dict(loop_mode=pkg.LOOP_HOST, small_bin=1, wave_bin=1, chunk_edges=64),
          # the caller's labels, without the degree-sorted copy
          dict(loop_mode=pkg.LOOP_PERSISTENT, relabel=-1),
-         dict(loop_mode=pkg.LOOP_HOST, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64)]
+         dict(loop_mode=pkg.LOOP_HOST, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64),
+         # captured level-step graph, replayed until the traversal ends
+         dict(loop_mode=pkg.LOOP_GRAPH),
+         dict(loop_mode=pkg.LOOP_GRAPH, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64)]
 
 
 @pytest.mark.parametrize("name,make,sources", SMALL_GRAPHS, ids=[x[0] for x in SMALL_GRAPHS])
@@ -111,7 +114,7 @@ def test_level_stats(gpu):
     s = int(gg.pick_sources(g, 1, seed=5)[0])
     ref = oracle.bfs(g, s)
     deg = g.degrees()
-    for mode in (pkg.LOOP_PERSISTENT, pkg.LOOP_HOST):
+    for mode in (pkg.LOOP_PERSISTENT, pkg.LOOP_HOST, pkg.LOOP_GRAPH):
         dg = pkg.DeviceGraph.from_csr(g, gpu)
         plan = pkg.Plan([dg], loop_mode=mode, collect_stats=True)
         plan.run(0, s)
@@ -343,3 +346,25 @@ def test_full_size_rmat24_ef16(gpu, scale):
             assert np.array_equal(p.cpu().numpy(), oracle.parent(g, ref))
         assert st.edges_scanned == oracle.edges_scanned(g, ref)
     plan.close()
+
+
+def test_graph_replays_match_eager(gpu):
+    """The captured level graph is replayed many times per traversal and across
+    traversals, with eager launches and synchronisations in between; every
+    replayed result equals the eager host-driven result and the oracle."""
+    import torch
+    g = gg.grid(200, 150, 0.02, seed=17)  # ~350 levels: ~44 replays per traversal
+    dg = pkg.DeviceGraph.from_csr(g, gpu)
+    pg = pkg.Plan([dg], loop_mode=pkg.LOOP_GRAPH)
+    ph = pkg.Plan([dg], loop_mode=pkg.LOOP_HOST)
+    for s in gg.pick_sources(g, 4, seed=18):
+        dg_, _, st = pg.run(0, int(s))
+        torch.cuda.synchronize()
+        dh, _, _ = ph.run(0, int(s))
+        torch.cuda.synchronize()
+        ref = oracle.bfs(g, int(s))
+        assert np.array_equal(dg_.cpu().numpy(), ref)
+        assert np.array_equal(dh.cpu().numpy(), ref)
+        assert st.levels == int(ref.max()) + 1
+    pg.close()
+    ph.close()
