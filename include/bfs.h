@@ -104,6 +104,9 @@ typedef struct {
                               (level loop, register budget, grid size, degree-bin tier
                               thresholds) and keeps the fastest; explicit option values
                               are never overridden */
+  int32_t hot_words;       /* relabelled graphs: visited words each expansion block keeps in
+                              LDS on large levels; 0 = tuned, -1 = none */
+  int32_t reserved;
 } bfs_options;
 
 /* Fills *o with defaults (all zero / NULL, loop_mode AUTO). */
@@ -158,6 +161,7 @@ typedef struct {
   int32_t chunk_edges;
   int32_t relabelled;       /* 1 if bfs_run traverses the degree-sorted copy */
   float tuned_ms;           /* best traversal time seen by the autotuner (0: not tuned) */
+  int32_t hot_words;        /* visited words each expansion block keeps in LDS (0: none) */
 } bfs_tuning;
 
 /* Fills *out (host) with the settings of graph `graph`. */

@@ -43,7 +43,8 @@ class bfs_options(ctypes.Structure):
                 ("chunk_edges", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("batch_lanes", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
                 ("exchange", EXCHANGE_FN), ("exchange_ctx", ctypes.c_void_p),
-                ("relabel", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("relabel", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("hot_words", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class bfs_stats(ctypes.Structure):
@@ -57,7 +58,8 @@ class bfs_tuning(ctypes.Structure):
     _fields_ = [("loop_mode", ctypes.c_int32), ("persist_variant", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("small_bin", ctypes.c_int32),
                 ("wave_bin", ctypes.c_int32), ("chunk_edges", ctypes.c_int32),
-                ("relabelled", ctypes.c_int32), ("tuned_ms", ctypes.c_float)]
+                ("relabelled", ctypes.c_int32), ("tuned_ms", ctypes.c_float),
+                ("hot_words", ctypes.c_int32)]
 
 
 class bfs_query(ctypes.Structure):
@@ -176,7 +178,7 @@ class Plan:
 
     def __init__(self, graphs, *, loop_mode=LOOP_AUTO, small_bin=0, wave_bin=0, chunk_edges=0,
                  grid_blocks=0, batch_lanes=0, collect_stats=False, exchange=None, stream=None,
-                 relabel=0, autotune=0):
+                 relabel=0, autotune=0, hot_words=0):
         torch = _torch()
         L = lib()
         if isinstance(graphs, DeviceGraph):
@@ -192,6 +194,7 @@ class Plan:
         o.grid_blocks, o.batch_lanes, o.collect_stats = grid_blocks, batch_lanes, int(collect_stats)
         o.relabel = int(relabel)
         o.autotune = int(autotune)
+        o.hot_words = int(hot_words)
         self._exchange_py = exchange
         self._exchange_keep = None
         if exchange is not None:

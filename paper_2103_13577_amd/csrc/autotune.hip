@@ -134,6 +134,14 @@ bfs_status autotune_graphs(Plan *p) {
         if ((s = trial(c))) return s;
       }
     t = best;
+    // LDS copy of the hubs' visited bits (relabelled graphs only)
+    if (p->lay.rl_rp[gi] && best.loop_mode != BFS_LOOP_PERSISTENT && p->opt.hot_words == 0)
+      for (int hw : {1024, 2048, 4096}) {
+        Tuning c = best;
+        c.hot_words = hw;
+        if ((s = trial(c))) return s;
+      }
+    t = best;
     if (p->opt.chunk_edges <= 0)
       for (int cs : {11, 13}) {
         Tuning c = best;

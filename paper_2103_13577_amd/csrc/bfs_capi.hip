@@ -100,6 +100,11 @@ View bfs_plan_s::view(int32_t gi, int32_t *dist) const {
 
 int bfs_plan_s::wide_grid() const { return num_cus * std::max(bpc_expand, 1); }
 
+int bfs_plan_s::expand_grid(int hot_words) const {
+  if (hot_words <= 0) return wide_grid();
+  return num_cus * std::max(expand_blocks_per_cu((size_t)hot_words * 8), 1);
+}
+
 int bfs_plan_s::merge_grid(int64_t words) const {
   int64_t g = (words + kBlock - 1) / kBlock;
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, (int64_t)num_cus * 8));
@@ -188,7 +193,7 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
   p->coop = prop.cooperativeLaunch;
   p->bpc[0] = persistent_blocks_per_cu(0);
   p->bpc[1] = persistent_blocks_per_cu(1);
-  p->bpc_expand = expand_blocks_per_cu();
+  p->bpc_expand = expand_blocks_per_cu(0);
   p->persist_grid = o->grid_blocks;  // 0: chosen per graph
   if (o->grid_blocks > kBarrierGroup * kBarrierMaxGroups) {
     g_create_error = "grid_blocks above the grid barrier's limit of 2048";
@@ -260,6 +265,7 @@ bfs_status begin_impl(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist
   p->cur_relabel = relabel;
   p->level = 0;
   p->expanded_level = -1;
+  p->big_level = false;
   p->level_frontier.assign(1, (source >= g.v_begin && source < g.v_end) ? 1 : 0);
   View v = p->view(graph, dist);
   int grid = (int)std::min<int64_t>((g.n_global + kBlock - 1) / kBlock, (int64_t)p->num_cus * 16);
@@ -288,7 +294,9 @@ bfs_status bfs_expand(bfs_plan_t p, const uint64_t **local_next) {
   if (p->expanded_level == p->level) return p->fail(BFS_ERR_STATE, "level already expanded");
   const bool timed = p->time_levels && p->level < Plan::kTimedLevels;
   if (timed) (void)hipEventRecord(p->lev[p->level][0], p->stream);
-  hipError_t e = launch_expand(v, p->level, p->wide_grid(), p->stream);
+  // The LDS copy of the hub bits pays off only on large dense levels.
+  const int hot = (p->cur_relabel && p->big_level) ? p->tune[p->cur_graph].hot_words : 0;
+  hipError_t e = launch_expand(v, p->level, p->expand_grid(hot), hot, p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "expand launch");
   if (timed) (void)hipEventRecord(p->lev[p->level][1], p->stream);
   p->expanded_level = p->level;
@@ -326,6 +334,8 @@ bfs_status bfs_merge_frontier(bfs_plan_t p, const uint64_t *const *incoming, int
     if (global_new) *global_new = (int64_t)c.newcnt[p->level % 3];
     if (owned_new) *owned_new = (int64_t)c.ownedcnt[p->level % 3];
     if (!keep_next) {
+      // the next level is "big" when its frontier is a sizable share of the graph
+      p->big_level = (int64_t)c.ownedcnt[p->level % 3] * 16 >= v.n;
       if ((int)p->level_frontier.size() == p->level + 1)
         p->level_frontier.push_back((int64_t)c.ownedcnt[p->level % 3]);
       p->last_level_new = (int64_t)c.newcnt[p->level % 3];
@@ -364,7 +374,7 @@ namespace {
 
 bool same_tuning(const Tuning &a, const Tuning &b) {
   return a.small_bin == b.small_bin && a.wave_bin == b.wave_bin && a.chunk_shift == b.chunk_shift &&
-         a.sparse_div == b.sparse_div;
+         a.sparse_div == b.sparse_div && a.hot_words == b.hot_words;
 }
 
 // The captured graph of kGraphLevels level steps for graph gi (captured on
@@ -383,8 +393,9 @@ bfs_status graph_exec(bfs_plan_t p, int32_t gi, hipGraphExec_t &out) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return p->hip_fail(e, "hipStreamBeginCapture");
-  hipError_t el = enqueue_graph_levels(v, Plan::kGraphLevels, max_levels, p->wide_grid(),
-                                       p->merge_grid(v.words), p->cap_stream);
+  const int hot = p->cur_relabel ? p->tune[gi].hot_words : 0;
+  hipError_t el = enqueue_graph_levels(v, Plan::kGraphLevels, max_levels, p->expand_grid(hot),
+                                       p->merge_grid(v.words), hot, p->cap_stream);
   e = hipStreamEndCapture(p->cap_stream, &g);
   if (el != hipSuccess) e = el;
   if (e != hipSuccess) {
@@ -538,6 +549,7 @@ bfs_status bfs_plan_tuning(bfs_plan_t p, int32_t graph, bfs_tuning *out) {
   out->chunk_edges = 1 << t.chunk_shift;
   out->relabelled = (p->lay.rl_rp.size() > (size_t)graph && p->lay.rl_rp[graph]) ? 1 : 0;
   out->tuned_ms = t.tuned_ms;
+  out->hot_words = t.hot_words;
   return BFS_OK;
 }
 

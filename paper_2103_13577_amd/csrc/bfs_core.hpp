@@ -88,7 +88,7 @@ __host__ __device__ __forceinline__ int tier_of_bin(int b, int small_bin, int wa
 
 // Host launchers (bfs_kernels.hip).
 hipError_t launch_reset(const View &v, int64_t src, int grid, hipStream_t s);
-hipError_t launch_expand(const View &v, int level, int grid, hipStream_t s);
+hipError_t launch_expand(const View &v, int level, int grid, uint32_t hot_words, hipStream_t s);
 hipError_t launch_merge(const View &v, const MergeArgs &a, int grid, hipStream_t s);
 hipError_t launch_clear_stats_row(const View &v, int level, hipStream_t s);
 hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, hipStream_t s);
@@ -96,8 +96,8 @@ hipError_t launch_persistent(const View &v, int max_levels, int grid, int varian
 // Enqueues `levels` graph-launched level steps (expand, merge, advance) on s;
 // used while capturing a hipGraph.
 hipError_t enqueue_graph_levels(const View &v, int levels, int max_levels, int expand_grid,
-                                int merge_grid, hipStream_t s);
+                                int merge_grid, uint32_t hot_words, hipStream_t s);
 int persistent_blocks_per_cu(int variant);
-int expand_blocks_per_cu();
+int expand_blocks_per_cu(size_t lds_bytes);
 
 }  // namespace bfsk

@@ -97,12 +97,22 @@ __device__ __forceinline__ int32_t load_col(const int32_t *col, int64_t e) {
 
 // K independent probes: all visited words are requested before any is
 // tested, then all next words, so each lane keeps K random loads in flight.
+// Copy of the first `words` visited words in LDS (the hubs' bits once the
+// graph is relabelled by degree); words == 0 disables it.
+struct HotCache {
+  const uint64_t *lds;
+  uint32_t words;
+};
+
 template <int K>
 __device__ __forceinline__ void probe_batch(const View &v, const int32_t (&u)[K],
-                                            const bool (&ok)[K]) {
+                                            const bool (&ok)[K], HotCache hot) {
   uint64_t vis[K], nx[K];
 #pragma unroll
-  for (int j = 0; j < K; ++j) vis[j] = ok[j] ? v.visited[(uint32_t)u[j] >> 6] : ~0ull;
+  for (int j = 0; j < K; ++j) {
+    const uint32_t w = (uint32_t)u[j] >> 6;
+    vis[j] = !ok[j] ? ~0ull : (w < hot.words ? hot.lds[w] : v.visited[w]);
+  }
   bool need[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) need[j] = !((vis[j] >> (u[j] & 63)) & 1ull);
@@ -189,9 +199,10 @@ constexpr int kUnrollSmall = 8;  // edges per lane in flight (lane-group tier)
 
 template <bool SPARSE, int K>
 __device__ __forceinline__ void probe_dispatch(const View &v, const int32_t (&u)[K],
-                                               const bool (&ok)[K], int L, SparseAcc &acc) {
+                                               const bool (&ok)[K], int L, SparseAcc &acc,
+                                               HotCache hot) {
   if (SPARSE) probe_batch_sparse<K>(v, u, ok, L, acc);
-  else probe_batch<K>(v, u, ok);
+  else probe_batch<K>(v, u, ok, hot);
 }
 
 // Largest s in [0, n) with a[s] <= key (a ascending, a[0] == 0 <= key).
@@ -209,7 +220,8 @@ __device__ __forceinline__ uint32_t upper_slot(const uint32_t *a, uint32_t n, ui
 // L-1, not written before level L+1). Every loop below runs the same number
 // of iterations on all lanes of a wavefront (queue-only levels use ballots).
 template <bool SPARSE>
-__device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t nvb) {
+__device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t nvb,
+                             HotCache hot = HotCache{nullptr, 0}) {
   __shared__ int64_t s_lo, s_hi;
   __shared__ uint64_t s_acc[3][kWavesPerBlock];
   const int cur = level % kRing;
@@ -253,7 +265,7 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
         ok[j] = e < hi;
         u[j] = ok[j] ? load_col(v.col, e) : 0;
       }
-      probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc);
+      probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc, hot);
     }
     __syncthreads();
   }
@@ -272,7 +284,7 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
         ok[j] = k < e;
         u[j] = ok[j] ? load_col(v.col, k) : 0;
       }
-      probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc);
+      probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc, hot);
     }
   }
 
@@ -308,7 +320,7 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
         ok[j] = e < total;
         u[j] = ok[j] ? load_col(v.col, sk + (e - xk)) : 0;
       }
-      probe_dispatch<SPARSE, kUnrollSmall>(v, u, ok, level, acc);
+      probe_dispatch<SPARSE, kUnrollSmall>(v, u, ok, level, acc, hot);
     }
   }
 
@@ -567,8 +579,20 @@ __device__ void merge_phase(const View &v, const MergeArgs &a, uint32_t vb_id, u
 // kernels
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock) k_expand(View v, int level) {
-  expand_phase<false>(v, level, blockIdx.x, gridDim.x);
+// Loads visited words [0, words) into this block's LDS copy.
+__device__ __forceinline__ HotCache load_hot(const View &v, uint64_t *lds, uint32_t words) {
+  words = (uint32_t)min<int64_t>(words, v.words);
+  for (uint32_t i = threadIdx.x; i < words; i += kBlock) lds[i] = v.visited[i];
+  __syncthreads();
+  return HotCache{lds, words};
+}
+
+// hot_words > 0: the block keeps the first hot_words visited words in LDS
+// (the launch must provide hot_words * 8 bytes of dynamic LDS).
+__global__ void __launch_bounds__(kBlock) k_expand(View v, int level, uint32_t hot_words) {
+  extern __shared__ uint64_t s_hot[];
+  if (hot_words) expand_phase<false>(v, level, blockIdx.x, gridDim.x, load_hot(v, s_hot, hot_words));
+  else expand_phase<false>(v, level, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(kBlock) k_merge(View v, MergeArgs a) {
@@ -589,13 +613,25 @@ __device__ __forceinline__ bool level_is_sparse(const View &v, int L) {
   return v.sparse_div > 0 && fsize * (uint64_t)v.sparse_div < (uint64_t)v.words;
 }
 
-__global__ void __launch_bounds__(kBlock) k_expand_g(View v) {
+__global__ void __launch_bounds__(kBlock) k_expand_g(View v, uint32_t hot_words) {
+  extern __shared__ uint64_t s_hot[];
   if (load_relaxed_i32(&v.ctl->gdone)) return;
   const int L = load_relaxed_i32(&v.ctl->glevel);
   View w = v;
   w.dist = v.ctl->gdist;
-  if (level_is_sparse(w, L)) expand_phase<true>(w, L, blockIdx.x, gridDim.x);
-  else expand_phase<false>(w, L, blockIdx.x, gridDim.x);
+  if (level_is_sparse(w, L)) {
+    expand_phase<true>(w, L, blockIdx.x, gridDim.x);
+    return;
+  }
+  // the LDS copy of the hub bits pays off only when the frontier is large
+  const int cur = L % kRing;
+  const uint64_t fsize = (uint64_t)load_relaxed32(&w.ctl->qn[cur][0]) +
+                         load_relaxed32(&w.ctl->qn[cur][1]) +
+                         (load_relaxed64(&w.ctl->heavy[cur]) >> kHeavyShift);
+  if (hot_words && fsize * 16 >= (uint64_t)w.n)
+    expand_phase<false>(w, L, blockIdx.x, gridDim.x, load_hot(w, s_hot, hot_words));
+  else
+    expand_phase<false>(w, L, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(kBlock) k_merge_g(View v) {
@@ -630,9 +666,9 @@ __global__ void k_advance_g(View v, int max_levels) {
 }
 
 hipError_t enqueue_graph_levels(const View &v, int levels, int max_levels, int expand_grid,
-                                int merge_grid, hipStream_t s) {
+                                int merge_grid, uint32_t hot_words, hipStream_t s) {
   for (int i = 0; i < levels; ++i) {
-    hipLaunchKernelGGL(k_expand_g, dim3(expand_grid), dim3(kBlock), 0, s, v);
+    hipLaunchKernelGGL(k_expand_g, dim3(expand_grid), dim3(kBlock), hot_words * 8, s, v, hot_words);
     hipLaunchKernelGGL(k_merge_g, dim3(merge_grid), dim3(kBlock), 0, s, v);
     hipLaunchKernelGGL(k_advance_g, dim3(1), dim3(64), 0, s, v, max_levels);
   }
@@ -748,8 +784,8 @@ hipError_t launch_reset(const View &v, int64_t src, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_expand(const View &v, int level, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_expand, dim3(grid), dim3(kBlock), 0, s, v, level);
+hipError_t launch_expand(const View &v, int level, int grid, uint32_t hot_words, hipStream_t s) {
+  hipLaunchKernelGGL(k_expand, dim3(grid), dim3(kBlock), hot_words * 8, s, v, level, hot_words);
   return hipGetLastError();
 }
 
@@ -768,10 +804,13 @@ hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, 
   return hipGetLastError();
 }
 
-// Co-resident blocks per CU of the per-phase expansion kernel.
-int expand_blocks_per_cu() {
+// Co-resident blocks per CU of the per-phase expansion kernel with the given
+// dynamic LDS bytes.
+int expand_blocks_per_cu(size_t lds_bytes) {
   int nb = 0;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_expand, kBlock, 0) == hipSuccess ? nb : 0;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_expand, kBlock, lds_bytes) == hipSuccess
+             ? nb
+             : 0;
 }
 
 // Co-resident blocks per CU for the persistent kernel (variant 0 or 1).

@@ -126,6 +126,8 @@ bfs_status choose_tuning(Plan *p) {
     Tuning &t = p->tune[i];
     if (p->opt.small_bin > 0) t.small_bin = p->opt.small_bin;
     if (p->opt.wave_bin > 0) t.wave_bin = p->opt.wave_bin;
+    if (p->opt.hot_words > 0) t.hot_words = p->opt.hot_words;
+    if (t.hot_words > 16384) return p->fail(BFS_ERR_ARG, "hot_words above 16384 (128 KB of LDS)");
     if (p->opt.chunk_edges > 0) {
       int s = 0;
       while ((1 << s) < p->opt.chunk_edges && s < 30) ++s;

@@ -48,6 +48,7 @@ struct Tuning {
   int32_t persist_grid = 0;     // blocks of the cooperative launch
   int32_t loop_mode = 0;        // chosen level loop (BFS_LOOP_HOST or BFS_LOOP_PERSISTENT)
   float tuned_ms = 0.f;         // best time seen by the autotuner
+  int32_t hot_words = 0;        // visited words kept in LDS by each expansion block (0: off)
 };
 
 struct BatchState;  // batched / serving state (msbfs.hip)
@@ -67,6 +68,7 @@ struct bfs_plan_s {
   int persist_grid = 0;  // caller's grid_blocks (0: per-graph choice)
   int bpc[2] = {0, 0};   // co-resident blocks per CU of the two persistent variants
   int bpc_expand = 0;    // co-resident blocks per CU of the per-phase expansion
+  int expand_grid(int hot_words) const;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   static constexpr int kTimedLevels = 64;
   hipEvent_t lev[kTimedLevels][3] = {};  // per level: before expand, after expand, after merge
@@ -82,6 +84,7 @@ struct bfs_plan_s {
   bool cur_relabel = false;  // the current traversal runs on the relabelled copy
   int32_t level = 0;
   int32_t expanded_level = -1;  // last level bfs_expand ran for
+  bool big_level = false;       // the current level's frontier is large (host loop)
   int32_t persistent_levels = 0;
   int64_t last_level_new = 0;
   float last_ms = 0.f;

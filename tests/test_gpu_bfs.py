@@ -49,6 +49,9 @@ MODES = [dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST),
          dict(loop_mode=pkg.LOOP_HOST, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64),
          # captured level-step graph, replayed until the traversal ends
          dict(loop_mode=pkg.LOOP_GRAPH),
+         # LDS copy of the hubs' visited bits on large levels
+         dict(loop_mode=pkg.LOOP_HOST, hot_words=64),
+         dict(loop_mode=pkg.LOOP_GRAPH, hot_words=2048, small_bin=9),
          dict(loop_mode=pkg.LOOP_GRAPH, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64)]
 
 
