@@ -337,41 +337,34 @@ def run_serve(args):
 
     hashes = [None] * nq
     done_t = np.zeros(nq)
-    tickets = {}
-    start = [None]
-    lock_err = []
+    tk_info = {}        # ticket -> (query, graph, buffer)
+    state = {"submitted": 0, "completed": 0, "done_submitting": False}
+    errors = []
 
     def consumer():
-        pending = set()
         while True:
             with cv:
-                while not tickets and len(pending) == 0 and not (start[0] == "done"):
-                    cv.wait(0.01)
-                for k, v in list(tickets.items()):
-                    pending.add(k)
-                    del tickets[k]
-                if not pending and start[0] == "done":
+                if state["done_submitting"] and state["completed"] == state["submitted"]:
                     return
-            for i in list(pending):
-                tk, gi, bi = i
+            for tk in plan.batch_poll(1024, timeout_us=2000):
                 try:
                     r = plan.batch_wait(tk, timeout_us=0)
+                    ok = True
                 except pkg.BfsError as e:
-                    if e.status == 8:
-                        continue
-                    lock_err.append(str(e))
-                    pending.discard(i)
-                    continue
-                q = tk_query[tk]
-                done_t[q] = r.complete_ns * 1e-9
-                hashes[q] = out_hash(pools[gi][bi])
-                pending.discard(i)
+                    errors.append(str(e))
+                    ok = False
+                with cv:
+                    while tk not in tk_info:  # completed before the submitter recorded it
+                        cv.wait()
+                    q, gi, bi = tk_info.pop(tk)
+                if ok:
+                    done_t[q] = r.complete_ns * 1e-9
+                    hashes[q] = out_hash(pools[gi][bi])
                 with cv:
                     free[gi].append(bi)
+                    state["completed"] += 1
                     cv.notify_all()
-            time.sleep(0.0002)
 
-    tk_query = {}
     th = threading.Thread(target=consumer, daemon=True)
     th.start()
     t_start = time.perf_counter()
@@ -386,14 +379,13 @@ def run_serve(args):
             while not free[gi]:
                 cv.wait()
             bi = free[gi].pop()
+            state["submitted"] += 1
         tk = plan.batch_submit([(gi, int(srcs[q]), pools[gi][bi])], pkg.BATCH_STREAMING)
-        tk_query[tk] = q
         with cv:
-            tickets[(tk, gi, bi)] = True
+            tk_info[tk] = (q, gi, bi)
             cv.notify_all()
     with cv:
-        start[0] = "done"
-        cv.notify_all()
+        state["done_submitting"] = True
     th.join()
     t_end = max(done_t)
     arr_abs = t_start_mono + arrivals  # steady-clock time of each arrival
@@ -446,7 +438,7 @@ def run_serve(args):
                        "sample": int(samp.size)},
         "speedup_qps_vs_plain": round(served_qps / plain_qps, 2),
         "exact_sample": f"{exact}/{samp.size} served answers equal to bfs_run (64-bit hash)",
-        "errors": lock_err[:3],
+        "errors": errors[:3],
     }
     plan.close()
     single.close()

@@ -260,6 +260,15 @@ bfs_status bfs_batch_submit(bfs_plan_t p, const bfs_query *q, int32_t nq, uint32
 bfs_status bfs_batch_wait(bfs_plan_t p, uint64_t ticket, int64_t timeout_us,
                           bfs_batch_result *r);
 
+/*
+ * Completion queue of the serving loop: moves up to max ids of tickets that
+ * finished since the previous poll into done[] (host) and sets *n. Waits up
+ * to timeout_us (< 0: forever) when none is ready; *n = 0 on timeout. A
+ * polled ticket can still be passed to bfs_batch_wait / bfs_batch_times.
+ */
+bfs_status bfs_batch_poll(bfs_plan_t p, uint64_t *done, int32_t max, int32_t *n,
+                          int64_t timeout_us);
+
 /* Per-query completion times (host steady-clock ns) of a finished streaming
  * ticket, in submission order. */
 bfs_status bfs_batch_times(bfs_plan_t p, uint64_t ticket, int64_t *complete_ns, int32_t nq);

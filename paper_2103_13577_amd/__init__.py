@@ -104,6 +104,7 @@ def lib():
         "bfs_batch_submit": (i32, [vp, ctypes.POINTER(bfs_query), i32, u32, ctypes.POINTER(u64)]),
         "bfs_batch_wait": (i32, [vp, u64, i64, ctypes.POINTER(bfs_batch_result)]),
         "bfs_batch_times": (i32, [vp, u64, vp, i32]),
+        "bfs_batch_poll": (i32, [vp, vp, i32, ctypes.POINTER(i32), i64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -116,7 +117,7 @@ def lib():
 EXPORTED = ("bfs_options_default", "bfs_workspace_size", "bfs_plan_create", "bfs_plan_destroy",
             "bfs_last_error", "bfs_run", "bfs_begin", "bfs_expand", "bfs_merge_frontier",
             "bfs_finish", "bfs_level_stats", "bfs_plan_tuning", "bfs_batch_submit",
-            "bfs_batch_wait", "bfs_batch_times")
+            "bfs_batch_wait", "bfs_batch_times", "bfs_batch_poll")
 
 
 class BfsError(RuntimeError):
@@ -319,6 +320,15 @@ class Plan:
         r = bfs_batch_result()
         self._check(lib().bfs_batch_wait(self.h, ticket, timeout_us, ctypes.byref(r)))
         return r
+
+    def batch_poll(self, max_tickets: int = 1024, timeout_us: int = -1) -> list:
+        """Ids of tickets finished since the previous poll (may be empty on
+        timeout)."""
+        buf = np.zeros(max_tickets, dtype=np.uint64)
+        n = ctypes.c_int32(0)
+        self._check(lib().bfs_batch_poll(self.h, buf.ctypes.data, max_tickets, ctypes.byref(n),
+                                         timeout_us))
+        return [int(x) for x in buf[:n.value]]
 
     def batch_times(self, ticket: int, nq: int) -> np.ndarray:
         out = np.zeros(nq, dtype=np.int64)

@@ -47,12 +47,17 @@ bfs_status pick_source(Plan *p, size_t gi, int64_t &src) {
   return BFS_OK;
 }
 
-// Median of three timed traversals after one warm-up.
-bfs_status time_config(Plan *p, int32_t gi, int64_t src, float &ms) {
+// Median of three timed traversals after one warm-up (the warm-up alone
+// when it is already three times slower than the best so far).
+bfs_status time_config(Plan *p, int32_t gi, int64_t src, float best, float &ms) {
   int32_t *dist = (int32_t *)((char *)p->ws + p->lay.tune_dist);
   bfs_stats st;
   bfs_status s = bfs_run(p, gi, src, dist, nullptr, &st);
   if (s) return s;
+  if (st.ms > 3.f * best) {
+    ms = st.ms;
+    return BFS_OK;
+  }
   float t[3];
   for (float &x : t) {
     s = bfs_run(p, gi, src, dist, nullptr, &st);
@@ -79,7 +84,7 @@ bfs_status autotune_graphs(Plan *p) {
       const Tuning keep = t;
       t = c;
       float ms = 0.f;
-      bfs_status r = time_config(p, (int32_t)gi, src, ms);
+      bfs_status r = time_config(p, (int32_t)gi, src, best_ms, ms);
       if (r == BFS_OK && ms < best_ms) {
         best_ms = ms;
         best = c;

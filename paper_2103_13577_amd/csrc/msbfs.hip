@@ -68,6 +68,7 @@ struct BatchState {
   std::vector<uint64_t> active;              // [ng*lw]
   std::vector<uint64_t> dirty;               // [ng*lw] bits to clear before reuse
   std::map<uint64_t, MsTicket> tickets;
+  std::deque<uint64_t> completed;  // tickets finished and not yet polled
   uint64_t next_ticket = 1;
   bool stop = false;
   std::string worker_error;
@@ -339,6 +340,7 @@ bool BatchState::step(std::unique_lock<std::mutex> &lk) {
         t.status = e != hipSuccess ? BFS_ERR_HIP : BFS_ERR_DEVICE;
         t.done += 1;
         t.complete_ns = t_end;
+        if (t.done == t.nq) completed.push_back(slot_q[s].ticket);
       }
     std::fill(active.begin(), active.end(), 0);
     stop = true;
@@ -364,7 +366,10 @@ bool BatchState::step(std::unique_lock<std::mutex> &lk) {
       }
       t.times[mq.index_in_ticket] = t_end;
       t.done += 1;
-      if (t.done == t.nq) t.complete_ns = t_end;
+      if (t.done == t.nq) {
+        t.complete_ns = t_end;
+        completed.push_back(mq.ticket);
+      }
       active[i] &= ~(1ull << b);
       dirty[i] |= 1ull << b;
     }
@@ -436,7 +441,10 @@ bfs_status bfs_batch_submit(bfs_plan_t p, const bfs_query *q, int32_t nq, uint32
       mq.index_in_ticket = i;
       b->pending[mq.graph].push_back(mq);
     }
-    if (nq == 0) tk.complete_ns = tk.submit_ns;
+    if (nq == 0) {
+      tk.complete_ns = tk.submit_ns;
+      b->completed.push_back(t);
+    }
     *ticket = t;
   }
   b->cv_work.notify_all();
@@ -468,6 +476,25 @@ bfs_status bfs_batch_wait(bfs_plan_t p, uint64_t ticket, int64_t timeout_us, bfs
     const bfs_status st = t.status;
     return p->fail(st, st == BFS_ERR_DEPTH ? "a uint8 distance exceeded 254" : b->worker_error);
   }
+  return BFS_OK;
+}
+
+bfs_status bfs_batch_poll(bfs_plan_t p, uint64_t *done, int32_t max, int32_t *n,
+                          int64_t timeout_us) {
+  if (!p) return BFS_ERR_ARG;
+  BatchState *b = p->batch;
+  if (!b) return p->fail(BFS_ERR_CAPACITY, "plan has no lane memory for batched queries");
+  if (!done || !n || max <= 0) return p->fail(BFS_ERR_ARG, "bad poll buffer");
+  std::unique_lock<std::mutex> lk(b->mu);
+  auto ready = [&] { return !b->completed.empty() || b->stop; };
+  if (timeout_us < 0) b->cv_done.wait(lk, ready);
+  else b->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
+  int32_t k = 0;
+  while (k < max && !b->completed.empty()) {
+    done[k++] = b->completed.front();
+    b->completed.pop_front();
+  }
+  *n = k;
   return BFS_OK;
 }
 

@@ -108,6 +108,10 @@ def test_streaming_alone_equals_in_mix(gpu):
         tickets.append((plan.batch_submit(batch, pkg.BATCH_STREAMING), len(batch)))
         items += batch
         time.sleep(0.002)
+    seen = set()
+    while len(seen) < len(tickets):
+        seen.update(plan.batch_poll(64, timeout_us=2_000_000))
+    assert seen == {t for t, _ in tickets}
     for t, nq in tickets:
         plan.batch_wait(t)
         times = plan.batch_times(t, nq)
