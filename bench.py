@@ -124,7 +124,7 @@ def run_single(args, name, scale, ef):
     dg = pkg.DeviceGraph.from_csr(g, dev)
     plan = pkg.Plan([dg], loop_mode=args.loop_mode, grid_blocks=args.grid_blocks,
                     small_bin=args.small_bin, wave_bin=args.wave_bin, chunk_edges=args.chunk_edges,
-                    relabel=args.relabel, autotune=args.autotune)
+                    relabel=args.relabel, autotune=args.autotune, hot_words=args.hot_words)
     srcs = gg.pick_sources(g, args.warmup + args.steps, seed=sseed)
     dist = torch.empty(g.n, dtype=torch.int32, device=dev)
     for s in srcs[:args.warmup]:
@@ -156,6 +156,7 @@ def run_single(args, name, scale, ef):
         achieved = float(np.sum(k_bytes) / (np.sum(exp_ms) * 1e-3) / 1e9)
         per_launch_bytes = float(np.sum(k_bytes) / np.sum(launches))
         avg_launch_ms = float(np.sum(exp_ms) / np.sum(launches))
+        n_launches = int(np.sum(launches))
     else:
         # device-resident loop: one launch per traversal, which also writes
         # each reached vertex's distance (4 B)
@@ -164,6 +165,7 @@ def run_single(args, name, scale, ef):
         achieved = float(np.mean(k_bytes) / (np.mean(loop_ms) * 1e-3) / 1e9)
         per_launch_bytes = float(np.mean(k_bytes))
         avg_launch_ms = float(np.mean(loop_ms))
+        n_launches = len(stats)
     traffic = measured_traffic(kname, per_launch_bytes)
     whole_bytes = np.array([metrics.bytes_single_source(e, r, g.n) for e, r in zip(edges, reached)])
     out = {
@@ -188,7 +190,7 @@ def run_single(args, name, scale, ef):
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": kname,
                      "bytes_per_launch": int(per_launch_bytes),
-                     "avg_launch_ms": round(avg_launch_ms, 4)},
+                     "avg_launch_ms": round(avg_launch_ms, 4), "launches": n_launches},
         "detail": {
             "gteps_trimmed_mean_time": round(metrics.gteps(np.mean(edges), metrics.trimmed_mean(ms) * 1e-3), 3),
             "gteps_whole_graph_convention": round(metrics.harmonic_mean(g.m / (ms * 1e-3) / 1e9), 3),
@@ -555,33 +557,57 @@ def run_share29(args):
     return out
 
 
+def _bench_line(log_path):
+    """The JSON line a bench.py run printed into its log."""
+    with open(log_path) as f:
+        for line in f:
+            if line.startswith('{"metric"'):
+                return json.loads(line)
+    raise SystemExit(f"no bench JSON line in {log_path}")
+
+
+def _short(name):
+    return name.split("(")[0].split("::")[-1].strip('"')
+
+
 def summarize_pmc(args):
     """Writes profiles/traffic_rmat24.json from rocprofv3 --pmc runs: the mean
-    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of each kernel, scaled by what
-    the same counters read for a plain device copy of known size."""
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of each kernel over the timed
+    region's launches (the last `launches` dispatches named in the run's bench
+    line), scaled by what the same counters read for a plain device copy of
+    known size."""
     import csv
     from collections import defaultdict
 
-    def per_kernel(d, counter):
-        tot, n = defaultdict(float), defaultdict(set)
+    fd, wd, cfd, cwd, fetch_log = args.summarize_pmc
+    line = _bench_line(fetch_log)
+    timed = line["roofline"].get("launches", 0)
+
+    def per_kernel(d, counter, last=0):
+        vals = defaultdict(lambda: defaultdict(float))
         with open(os.path.join(d, "run_counter_collection.csv")) as f:
             for r in csv.DictReader(f):
                 if r["Counter_Name"] != counter:
                     continue
-                k = r["Kernel_Name"].split("(")[0].split("::")[-1]
-                tot[k] += float(r["Counter_Value"])
-                n[k].add(r["Dispatch_Id"])
-        return {k: tot[k] / len(n[k]) for k in tot}, {k: len(n[k]) for k in n}
+                vals[_short(r["Kernel_Name"])][int(r["Dispatch_Id"])] += float(r["Counter_Value"])
+        out, cnt = {}, {}
+        for k, per in vals.items():
+            ids = sorted(per)
+            if last and k in ("k_expand", "k_merge"):
+                ids = ids[-last:]
+            out[k] = sum(per[i] for i in ids) / len(ids)
+            cnt[k] = len(ids)
+        return out, cnt
 
-    fd, wd, cfd, cwd = args.summarize_pmc
-    fetch, nf = per_kernel(fd, "FETCH_SIZE")
-    write, _ = per_kernel(wd, "WRITE_SIZE")
+    fetch, nf = per_kernel(fd, "FETCH_SIZE", timed)
+    write, _ = per_kernel(wd, "WRITE_SIZE", timed)
     cf, _ = per_kernel(cfd, "FETCH_SIZE")
     cw, _ = per_kernel(cwd, "WRITE_SIZE")
     copy_kib = args.copy_bytes / 1024.0
     ck = [k for k in cf if "copy" in k.lower()][0]
     fscale, wscale = copy_kib / cf[ck], copy_kib / cw[ck]
     out = {"workload": "R-MAT scale 24 edge factor 16, host-driven level loop",
+           "plan": line["config"].get("plan"),
            "kernel_source_hash": kernel_source_hash(),
            "copy_probe": {"bytes": args.copy_bytes, "fetch_kib": cf[ck], "write_kib": cw[ck],
                           "fetch_scale": fscale, "write_scale": wscale},
@@ -598,6 +624,48 @@ def summarize_pmc(args):
     with open(os.path.join(ROOT, "profiles", "traffic_rmat24.json"), "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
+
+
+def summarize_trace(args):
+    """Writes a short markdown summary of a rocprofv3 --kernel-trace --stats
+    run of bench.py: the command, the busiest kernels over the whole run, and
+    the dominant kernel's average duration over the timed region (its last
+    `launches` dispatches) next to what bench.py measured with HIP events."""
+    import csv
+    from collections import defaultdict
+
+    d, log, out_name, command = args.summarize_trace
+    line = _bench_line(log)
+    roof = line["roofline"]
+    kname, timed = roof["kernel"], roof.get("launches", 0)
+    rows = list(csv.DictReader(open(os.path.join(d, "run_kernel_stats.csv"))))
+    durs = defaultdict(list)
+    with open(os.path.join(d, "run_kernel_trace.csv")) as f:
+        for r in csv.DictReader(f):
+            durs[_short(r["Kernel_Name"])].append(
+                (int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    sel = sorted(durs.get(kname, []))
+    if timed:
+        sel = sel[-timed:]
+    avg_ms = sum(x for _, x in sel) / max(len(sel), 1) / 1e6
+    md = [f"# rocprofv3 kernel trace: {line['config']['workload']}", "",
+          "Command (from the repository root):", "", "```", command, "```", "",
+          f"bench.py line: value {line['value']} {line['unit']}, ms_per_step {line['ms_per_step']}, "
+          f"plan {json.dumps(line['config'].get('plan'))}", "",
+          f"Dominant kernel `{kname}`: {len(sel)} launches in the timed region, "
+          f"average {avg_ms:.4f} ms (rocprofv3) vs {roof['avg_launch_ms']} ms (HIP events in "
+          f"bench.py); roofline achieved {roof['achieved']} {roof['unit']} "
+          f"({roof['frac']} of {roof['peak']}), {roof['bytes_per_launch']} algorithmic bytes "
+          f"per launch.", "",
+          "Whole run (plan creation and autotuning included):", "",
+          "| kernel | calls | total ms | average us | share % |", "|---|---|---|---|---|"]
+    for r in rows[:12]:
+        md.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.2f} | "
+                  f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", out_name), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("\n".join(md))
 
 
 def copy_probe(nbytes):
@@ -625,6 +693,7 @@ def main():
     ap.add_argument("--chunk-edges", type=int, default=0)
     ap.add_argument("--relabel", type=int, default=0, help="0 auto, 1 on, -1 off")
     ap.add_argument("--autotune", type=int, default=0, help="0 auto, 1 on, -1 off")
+    ap.add_argument("--hot-words", type=int, default=0, help="0 tuned, -1 none")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=int, default=0)
@@ -633,8 +702,10 @@ def main():
     ap.add_argument("--serve-buffers", type=int, default=96)
     ap.add_argument("--serve-sample", type=int, default=200)
     ap.add_argument("--share-scale", type=int, default=29)
-    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
-                                                         "COPY_WRITE_DIR"))
+    ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                         "COPY_WRITE_DIR", "FETCH_RUN_LOG"))
+    ap.add_argument("--summarize-trace", nargs=4, metavar=("TRACE_DIR", "RUN_LOG", "OUT_NAME",
+                                                           "COMMAND"))
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -647,6 +718,9 @@ def main():
         return
     if args.summarize_pmc:
         summarize_pmc(args)
+        return
+    if args.summarize_trace:
+        summarize_trace(args)
         return
     if args.workload == "rmat24":
         out = run_single(args, "rmat24", 24, 16)

@@ -91,7 +91,7 @@ typedef struct {
   int32_t small_bin;       /* degree bins b < small_bin -> lane-group tier; 0 = tuned default */
   int32_t wave_bin;        /* bins small_bin <= b < wave_bin -> wave tier, else block tier */
   int32_t chunk_edges;     /* edges per block-tier work item (power of two); 0 = default */
-  int32_t grid_blocks;     /* workgroups for device-resident loops; 0 = fill the chip */
+  int32_t grid_blocks;     /* workgroups for device-resident loops; 0 = sized to the graph */
   int32_t batch_lanes;     /* 64-source lane words per graph for batched BFS; 0 = none */
   int32_t collect_stats;   /* nonzero: per-level frontier sizes and degree-bin histograms */
   bfs_exchange_fn exchange;
@@ -99,7 +99,7 @@ typedef struct {
   int32_t relabel;         /* whole graphs: 0 = automatic (on), 1 = on, -1 = off. A
                               relabelled copy sorted by descending degree is built at plan
                               creation (inside the workspace); results keep original ids */
-  int32_t autotune;        /* 0 = automatic (whole graphs with >= 2^22 edges), 1 = always,
+  int32_t autotune;        /* 0 = automatic (whole graphs with >= 2^16 edges), 1 = always,
                               -1 = never. The plan times a few traversals per candidate
                               (level loop, register budget, grid size, degree-bin tier
                               thresholds) and keeps the fastest; explicit option values

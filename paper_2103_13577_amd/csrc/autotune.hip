@@ -21,7 +21,7 @@ bool tune_wanted(const Plan *p, size_t gi) {
   if (a < 0 || p->opt.exchange) return false;
   const bfs_graph &g = p->graphs[gi];
   if (g.v_begin != 0 || g.v_end != g.n_global) return false;
-  if (a == 0 && g.m < (1ll << 22)) return false;
+  if (a == 0 && g.m < (1ll << 16)) return false;
   return true;
 }
 
@@ -102,15 +102,23 @@ bfs_status autotune_graphs(Plan *p) {
       loops.push_back(h);
     }
     if (p->coop && (p->opt.loop_mode == BFS_LOOP_AUTO || p->opt.loop_mode == BFS_LOOP_PERSISTENT)) {
+      // grids: all co-resident blocks, half of them, one block per CU and
+      // one per four CUs (fewer blocks make each grid barrier cheaper, which
+      // wins on small graphs)
       for (int var = 0; var < 2; ++var) {
         const int bpc = p->bpc[var];
-        for (int per_cu : {bpc, bpc / 2}) {
-          const int grid = std::min(per_cu * p->num_cus, kBarrierGroup * kBarrierMaxGroups);
-          if (per_cu <= 0 || grid <= 0) continue;
+        if (bpc <= 0) continue;
+        const int cap = std::min(bpc * p->num_cus, kBarrierGroup * kBarrierMaxGroups);
+        int last = -1;
+        for (int grid : {cap, (bpc / 2) * p->num_cus, p->num_cus, p->num_cus / 4}) {
+          grid = std::min(grid, cap);
+          if (p->persist_grid > 0) grid = p->persist_grid;
+          if (grid <= 0 || grid == last) continue;
+          last = grid;
           Tuning c = t;
           c.loop_mode = BFS_LOOP_PERSISTENT;
           c.persist_variant = var;
-          c.persist_grid = p->persist_grid > 0 ? p->persist_grid : grid;
+          c.persist_grid = grid;
           loops.push_back(c);
           if (p->persist_grid > 0) break;
         }

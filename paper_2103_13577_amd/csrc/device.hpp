@@ -79,12 +79,12 @@ __device__ __forceinline__ int32_t load_relaxed_i32(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier state. Arrival counters for groups of blocks and the
-// generation word each sit on their own 128-byte cache line, so the blocks
-// that poll the generation do not slow down the arriving atomics. Valid from
-// any initial generation; every counter must be 0 when no block is inside a
+// Grid barrier state. Arrival and release words of each group of blocks and
+// the global generation each sit on their own 128-byte cache line, so polling
+// is spread over many lines instead of hammering one. Valid from any initial
+// generation; every arrival counter must be 0 when no block is inside a
 // barrier (the last arriver of each level resets it).
-constexpr int kBarrierGroup = 32;      // blocks per first-level arrival counter
+constexpr int kBarrierGroup = 32;      // blocks per group
 constexpr int kBarrierMaxGroups = 64;  // up to 2048 blocks
 struct GridBarrier {
   uint32_t gen;
@@ -93,54 +93,70 @@ struct GridBarrier {
   uint32_t top;     // arrivals of group leaders
   uint32_t pad1[31];
   struct {
-    uint32_t count;
-    uint32_t pad[31];
+    uint32_t count;    // arrivals in the group
+    uint32_t release;  // generation last released to the group
+    uint32_t pad[30];
   } group[kBarrierMaxGroups];
 };
 
-// Spin limit per barrier wait: 2^20 polls separated by ~512-clock sleeps is
-// about 0.25 s, orders of magnitude above any legitimate wait for
-// co-resident blocks.
+// Spin limit per barrier wait: 2^20 polls separated by sleeps is well over
+// 0.1 s, orders of magnitude above any legitimate wait for co-resident blocks.
 constexpr uint32_t kSpinLimit = 1u << 20;
 
+// Polls with relaxed loads: an acquire load at agent scope invalidates the
+// CU's caches on every poll, which with many polling blocks evicts the working
+// set of the blocks still computing. The caller issues one acquire fence once
+// the word has moved.
+__device__ __forceinline__ bool spin_until_changed(const uint32_t *p, uint32_t old, int32_t *tripped) {
+  uint32_t spins = 0;
+  while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == old) {
+    __builtin_amdgcn_s_sleep(2);
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(tripped, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+  }
+  return true;
+}
+
 // All blocks of a cooperative launch (at most 2048) must call this the same
-// number of times. Each block reads the generation before it arrives (the
-// generation cannot move until every block has arrived). Arrival is a
-// two-level tree: the last block of each group of 32 arrives at the top
-// counter, and the last of those resets the counters and advances the
-// generation. Release/acquire at agent scope make every write before the
-// barrier visible to every read after it. If a wait exceeds the spin limit
-// the barrier marks `tripped` and lets the block continue, so the kernel
-// always terminates; the host reports the trip as an error.
+// number of times. Arrival is a two-level tree: the last block of each group
+// of 32 arrives at the top counter, and the last group leader resets the
+// counters and advances the global generation. Release is the same tree in
+// reverse: group leaders wait for the global generation and then release
+// their group through the group's own word, on which the other members wait.
+// Every block reads the word it waits on before it arrives (it cannot move
+// until that block has arrived). Release/acquire at agent scope make every
+// write before the barrier visible to every read after it. A wait that
+// exceeds the spin limit marks `tripped` and lets the block continue, so the
+// kernel always terminates; the host reports the trip as an error.
 __device__ __forceinline__ void grid_barrier(GridBarrier *b, uint32_t nblocks) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t g0 = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const uint32_t grp = blockIdx.x / kBarrierGroup;
     const uint32_t ngroups = (nblocks + kBarrierGroup - 1) / kBarrierGroup;
     const uint32_t in_grp = min((uint32_t)kBarrierGroup, nblocks - grp * kBarrierGroup);
-    bool last = false;
+    const uint32_t r0 =
+        __hip_atomic_load(&b->group[grp].release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t g0 = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const uint32_t a1 = __hip_atomic_fetch_add(&b->group[grp].count, 1u, __ATOMIC_ACQ_REL,
                                                __HIP_MEMORY_SCOPE_AGENT) + 1;
     if (a1 == in_grp) {
+      // group leader: arrive at the top, wait for the generation, release the group
       __hip_atomic_store(&b->group[grp].count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const uint32_t a2 =
           __hip_atomic_fetch_add(&b->top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
-      last = a2 == ngroups;
-    }
-    if (last) {
-      __hip_atomic_store(&b->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      uint32_t spins = 0;
-      while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-        __builtin_amdgcn_s_sleep(8);
-        if (++spins > kSpinLimit) {
-          __hip_atomic_store(&b->tripped, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
+      if (a2 == ngroups) {
+        __hip_atomic_store(&b->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        spin_until_changed(&b->gen, g0, &b->tripped);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
+      __hip_atomic_store(&b->group[grp].release, r0 + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      spin_until_changed(&b->group[grp].release, r0, &b->tripped);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }

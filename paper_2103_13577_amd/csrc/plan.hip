@@ -135,14 +135,19 @@ bfs_status choose_tuning(Plan *p) {
     }
     if (t.small_bin < 1 || t.wave_bin < t.small_bin || t.chunk_shift < 6)
       return p->fail(BFS_ERR_ARG, "bad tier thresholds");
-    // untuned default: the cooperative loop with the 64-VGPR budget and up to
-    // 8 blocks per CU, else launches per phase
+    // untuned default: the cooperative loop with the 64-VGPR budget, one
+    // block per 16K edges and vertices of the share (a small grid keeps the
+    // grid barriers of small graphs cheap), between a quarter of the CUs and
+    // 8 blocks per CU; else launches per phase
+    const int64_t m = p->graphs[i].m;
     t.persist_variant = p->bpc[1] > 0 ? 1 : 0;
     const int per_cu = std::min(p->bpc[t.persist_variant], 8);
-    t.persist_grid = std::min(per_cu * p->num_cus, kBarrierGroup * kBarrierMaxGroups);
+    const int64_t work_grid = (m + (p->graphs[i].v_end - p->graphs[i].v_begin) + (1 << 14) - 1) >> 14;
+    const int64_t max_grid = std::min(per_cu * p->num_cus, kBarrierGroup * kBarrierMaxGroups);
+    t.persist_grid = (int)std::max<int64_t>(
+        1, std::min<int64_t>(max_grid, std::max<int64_t>(work_grid, p->num_cus / 4)));
     t.loop_mode = (p->coop && per_cu > 0) ? BFS_LOOP_PERSISTENT : BFS_LOOP_HOST;
     // cstart entries are 32-bit: total chunks must stay below 2^32.
-    const int64_t m = p->graphs[i].m;
     if ((m >> t.chunk_shift) + (p->graphs[i].v_end - p->graphs[i].v_begin) >= (1ll << 32))
       return p->fail(BFS_ERR_ARG, "chunk_edges too small for this graph");
     // The workgroup-tier queue length shares a 64-bit counter with the chunk
