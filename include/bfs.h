@@ -84,11 +84,14 @@ typedef int32_t (*bfs_exchange_fn)(void *ctx, int32_t level, const uint64_t *loc
 #define BFS_LOOP_HOST 1       /* one launch per phase, host reads the new count */
 #define BFS_LOOP_PERSISTENT 2 /* whole traversal in one cooperative launch */
 #define BFS_LOOP_GRAPH 3      /* a captured hipGraph of 8 level steps, replayed until done */
+#define BFS_LOOP_CU 4         /* whole traversal in one workgroup with its bitmaps in LDS: whole
+                                 graphs with m < 2^25 whose three n-bit bitmaps fit in one
+                                 workgroup's LDS (else BFS_ERR_ARG when asked for explicitly) */
 
 typedef struct {
   void *hip_stream;        /* hipStream_t; NULL = the null stream */
   int32_t loop_mode;       /* BFS_LOOP_* */
-  int32_t small_bin;       /* degree bins b < small_bin -> lane-group tier; 0 = tuned default */
+  int32_t small_bin;       /* degree bins b < small_bin -> lane-group tier (1..24); 0 = tuned */
   int32_t wave_bin;        /* bins small_bin <= b < wave_bin -> wave tier, else block tier */
   int32_t chunk_edges;     /* edges per block-tier work item (power of two); 0 = default */
   int32_t grid_blocks;     /* workgroups for device-resident loops; 0 = sized to the graph */
@@ -105,7 +108,10 @@ typedef struct {
                               thresholds) and keeps the fastest; explicit option values
                               are never overridden */
   int32_t hot_words;       /* relabelled graphs: visited words each expansion block keeps in
-                              LDS on large levels; 0 = tuned, -1 = none */
+                              LDS on large levels; above 4096 words the expansion runs one
+                              1024-thread block per CU sharing the copy. At most (LDS bytes
+                              per workgroup - 1024) / 8, else BFS_ERR_ARG; 0 = tuned,
+                              -1 = none */
   int32_t reserved;
 } bfs_options;
 

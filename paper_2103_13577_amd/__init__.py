@@ -20,7 +20,7 @@ BFS_OK = 0
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_WORKSPACE", 3: "ERR_HIP", 4: "ERR_DEPTH",
                 5: "ERR_CAPACITY", 6: "ERR_EXCHANGE", 7: "ERR_STATE", 8: "ERR_TIMEOUT",
                 9: "ERR_DEVICE"}
-LOOP_AUTO, LOOP_HOST, LOOP_PERSISTENT, LOOP_GRAPH = 0, 1, 2, 3
+LOOP_AUTO, LOOP_HOST, LOOP_PERSISTENT, LOOP_GRAPH, LOOP_CU = 0, 1, 2, 3, 4
 OUT_U8, OUT_I32 = 0, 1
 BATCH_ONE_LAUNCH, BATCH_STREAMING = 1, 2
 NUM_BINS = 34

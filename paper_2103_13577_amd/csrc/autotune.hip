@@ -124,10 +124,20 @@ bfs_status autotune_graphs(Plan *p) {
         }
       }
     }
+    if (p->opt.loop_mode == BFS_LOOP_AUTO &&
+        cu_fits(p->graphs[gi].n_global, p->graphs[gi].m, true, p->max_lds)) {
+      Tuning c = t;
+      c.loop_mode = BFS_LOOP_CU;
+      loops.push_back(c);
+    }
     if (loops.empty()) loops.push_back(t);
     for (const Tuning &c : loops)
       if ((s = trial(c))) return s;
     t = best;
+    if (best.loop_mode == BFS_LOOP_CU) {  // the tier settings do not apply
+      t.tuned_ms = best_ms;
+      continue;
+    }
     // 2. tier thresholds (degree bins), each kept only if it helps
     if (p->opt.small_bin <= 0)
       for (int sb : {5, 7, 8, 9, 10, 11}) {
@@ -149,7 +159,8 @@ bfs_status autotune_graphs(Plan *p) {
     t = best;
     // LDS copy of the hubs' visited bits (relabelled graphs only)
     if (p->lay.rl_rp[gi] && best.loop_mode != BFS_LOOP_PERSISTENT && p->opt.hot_words == 0)
-      for (int hw : {1024, 2048, 4096}) {
+      for (int hw : {1024, 2048, 4096, 8192, 16384, 18432}) {
+        if ((int64_t)hw * 8 + 1024 > p->max_lds) continue;
         Tuning c = best;
         c.hot_words = hw;
         if ((s = trial(c))) return s;

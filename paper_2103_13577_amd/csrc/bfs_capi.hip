@@ -100,9 +100,11 @@ View bfs_plan_s::view(int32_t gi, int32_t *dist) const {
 
 int bfs_plan_s::wide_grid() const { return num_cus * std::max(bpc_expand, 1); }
 
-int bfs_plan_s::expand_grid(int hot_words) const {
+int bfs_plan_s::expand_grid(int hot_words) {
   if (hot_words <= 0) return wide_grid();
-  return num_cus * std::max(expand_blocks_per_cu((size_t)hot_words * 8), 1);
+  auto it = hot_bpc.find(hot_words);
+  if (it == hot_bpc.end()) it = hot_bpc.emplace(hot_words, expand_blocks_per_cu((uint32_t)hot_words)).first;
+  return num_cus * std::max(it->second, 1);
 }
 
 int bfs_plan_s::merge_grid(int64_t words) const {
@@ -193,8 +195,14 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
   p->coop = prop.cooperativeLaunch;
   p->bpc[0] = persistent_blocks_per_cu(0);
   p->bpc[1] = persistent_blocks_per_cu(1);
-  p->bpc_expand = expand_blocks_per_cu(0);
+  p->bpc_expand = expand_blocks_per_cu(0u);
+  p->max_lds = (int)prop.sharedMemPerBlock;
   p->persist_grid = o->grid_blocks;  // 0: chosen per graph
+  if (o->loop_mode < BFS_LOOP_AUTO || o->loop_mode > BFS_LOOP_CU) {
+    g_create_error = "unknown loop_mode";
+    delete p;
+    return BFS_ERR_ARG;
+  }
   if (o->grid_blocks > kBarrierGroup * kBarrierMaxGroups) {
     g_create_error = "grid_blocks above the grid barrier's limit of 2048";
     delete p;
@@ -445,8 +453,30 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
       mode = BFS_LOOP_HOST;
     }
   }
+  if (mode == BFS_LOOP_CU && !cu_fits(g.n_global, g.m, g.v_begin == 0 && g.v_end == g.n_global,
+                                      p->max_lds)) {
+    if (p->opt.loop_mode == BFS_LOOP_CU)
+      return p->fail(BFS_ERR_ARG, "one-workgroup loop needs a whole graph with m < 2^25 whose "
+                                  "three bitmaps fit in one workgroup's LDS");
+    mode = BFS_LOOP_HOST;
+  }
   const bool host_loop = mode == BFS_LOOP_HOST;
-  if (mode == BFS_LOOP_GRAPH) {
+  if (mode == BFS_LOOP_CU) {
+    View v = p->view(graph, dist);
+    const int max_levels = (int)std::min<int64_t>(g.n_global + 1, 1ll << 30);
+    e = hipEventRecord(p->ev[2], p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
+    e = launch_bfs_cu(v, source, max_levels, p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "one-workgroup launch");
+    e = hipEventRecord(ev1, p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
+    Ctl c;
+    s = p->read_ctl(c);
+    if (s) return s;
+    if (c.err) return p->fail(BFS_ERR_DEVICE, "level limit exceeded");
+    p->persistent_levels = c.levels;
+    p->level = c.levels;
+  } else if (mode == BFS_LOOP_GRAPH) {
     hipGraphExec_t ge = nullptr;
     s = graph_exec(p, graph, ge);
     if (s) return s;

@@ -12,6 +12,8 @@ constexpr int kNumBins = 34;   // degree bin 0 (degree 0) .. 33
 constexpr int kTiers = 3;      // lane-group, wavefront, chunked workgroup
 constexpr int kBlock = 256;    // threads per workgroup for the traversal kernels
 constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kWideBlock = 1024;      // threads per workgroup of the wide expansion
+constexpr uint32_t kNarrowHotMax = 4096;  // larger LDS hub copies use the wide expansion
 constexpr int kMaxStatLevels = 4096;
 constexpr int kHeavyShift = 40;  // packed heavy-tier counter: count << 40 | chunks
 constexpr uint64_t kChunkMask = (1ull << kHeavyShift) - 1;
@@ -98,6 +100,9 @@ hipError_t launch_persistent(const View &v, int max_levels, int grid, int varian
 hipError_t enqueue_graph_levels(const View &v, int levels, int max_levels, int expand_grid,
                                 int merge_grid, uint32_t hot_words, hipStream_t s);
 int persistent_blocks_per_cu(int variant);
-int expand_blocks_per_cu(size_t lds_bytes);
+int expand_blocks_per_cu(uint32_t hot_words);
+size_t cu_lds_bytes(int64_t words);
+bool cu_fits(int64_t n, int64_t m, bool whole, int max_lds);
+hipError_t launch_bfs_cu(const View &v, int64_t src, int max_levels, hipStream_t s);
 
 }  // namespace bfsk

@@ -1,0 +1,170 @@
+// Whole traversal of a small graph by one workgroup, its bitmaps in LDS.
+//
+// For graphs whose visited, frontier and next bitmaps fit in one workgroup's
+// LDS (n up to a few hundred thousand vertices on gfx950), a traversal is
+// bound by per-level latency, not by bandwidth: the grid barriers of a
+// cooperative launch (each one a device-scope release and acquire on every
+// block) or a launch per phase cost more than the level's work. Here one
+// 1024-thread workgroup runs the same level-synchronous top-down steps
+// (Algorithm 1; Algorithm 2 with a single compute node) with workgroup
+// barriers between phases:
+//   expand - each wavefront takes frontier words; the set bits' adjacency
+//            lists are dealt evenly over the 64 lanes (a wavefront prefix sum
+//            and a binary search over the shuffled prefix values), and every
+//            neighbour whose visited bit is clear is ORed into the LDS next
+//            bitmap;
+//   merge  - new = next & ~visited per word; the new vertices get distance
+//            level+1 and become the frontier.
+// The control block receives the level count, the reached count and the
+// edges scanned, as the other level loops leave them.
+
+#include <hip/hip_runtime.h>
+
+#include "bfs_core.hpp"
+
+namespace bfsk {
+
+namespace {
+
+constexpr int kCuBlock = 1024;
+constexpr int kCuWaves = kCuBlock / kWave;
+constexpr int kCuUnroll = 8;  // edges per lane in flight
+
+__device__ __forceinline__ void lds_or(uint64_t *p, uint64_t bit) {
+  (void)__hip_atomic_fetch_or(p, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Requires a whole graph (owned range [0, n)) with m < 2^25 edges, so one
+// wavefront's edge prefix sums fit in 32 bits, and 3 * words * 8 bytes of
+// dynamic LDS. dist was reset by k_reset.
+__global__ void __launch_bounds__(kCuBlock) k_bfs_cu(View v, int64_t src_caller, int max_levels) {
+  extern __shared__ uint64_t lds[];
+  const int64_t W = v.words;
+  uint64_t *vis = lds, *front = lds + W, *nxt = lds + 2 * W;
+  __shared__ uint32_t s_new[3];
+  __shared__ unsigned long long s_edges;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wave = tid / kWave;
+  const int64_t src = v.new_id ? (int64_t)v.new_id[src_caller] : src_caller;
+  for (int64_t w = tid; w < W; w += kCuBlock) {
+    const uint64_t b = (w == (src >> 6)) ? (1ull << (src & 63)) : 0ull;
+    vis[w] = b;
+    front[w] = b;
+    nxt[w] = 0ull;
+  }
+  if (tid == 0) {
+    s_new[0] = s_new[1] = s_new[2] = 0;
+    s_edges = 0;
+  }
+  __syncthreads();
+  uint64_t edges = 0;  // lane 0 of each wavefront: degrees of its frontier vertices
+  uint64_t reached = 1;
+  uint32_t nn = 0;
+  int L = 0;
+  for (;; ++L) {
+    // s_new[(L+1)%3] was last read two workgroup barriers ago; histogram row
+    // L+2 is first written by the merge of level L+1
+    if (tid == 0) s_new[(L + 1) % 3] = 0;
+    if (v.stats && L + 2 < kMaxStatLevels && tid < kNumBins) v.lvl_hist[(L + 2) * kNumBins + tid] = 0;
+    // expand
+    for (int64_t w = wave; w < W; w += kCuWaves) {
+      const uint64_t f = front[w];
+      if (f == 0ull) continue;
+      const int64_t x = w * 64 + lane;
+      int64_t start = 0;
+      int32_t deg = 0;
+      if ((f >> lane) & 1ull) {
+        start = v.rp[x];
+        deg = (int32_t)(v.rp[x + 1] - start);
+      }
+      const int32_t incl = wave_incl_scan32(deg);
+      const int32_t total = __shfl(incl, kWave - 1);
+      const int64_t rebase = start - (int64_t)(incl - deg);
+      if (lane == 0) edges += (uint64_t)total;
+      for (int32_t e0 = 0; e0 < total; e0 += kWave * kCuUnroll) {
+        int32_t u[kCuUnroll];
+        bool ok[kCuUnroll];
+#pragma unroll
+        for (int j = 0; j < kCuUnroll; ++j) {
+          const int32_t e = e0 + j * kWave + lane;
+          int k = 0;
+#pragma unroll
+          for (int step = 32; step >= 1; step >>= 1)
+            if (__shfl(incl, k + step - 1) <= e) k += step;
+          k = min(k, kWave - 1);
+          const int64_t rk = shfl64(rebase, k);
+          ok[j] = e < total;
+          u[j] = ok[j] ? __builtin_nontemporal_load(v.col + rk + e) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kCuUnroll; ++j) {
+          const uint32_t uw = (uint32_t)u[j] >> 6;
+          const uint64_t bit = 1ull << (u[j] & 63);
+          if (ok[j] && !(vis[uw] & bit) && !(nxt[uw] & bit)) lds_or(nxt + uw, bit);
+        }
+      }
+    }
+    __syncthreads();
+    // merge
+    uint32_t cnt = 0;
+    for (int64_t w = wave; w < W; w += kCuWaves) {
+      const uint64_t nw = nxt[w] & ~vis[w];
+      if (nw != 0ull) {
+        if ((nw >> lane) & 1ull) {
+          const int64_t x = w * 64 + lane;
+          v.dist[v.old_id ? (int64_t)v.old_id[x] : x] = L + 1;
+          if (v.stats && L + 1 < kMaxStatLevels)
+            atomic_add32(&v.lvl_hist[(L + 1) * kNumBins + degree_bin(v.rp[x + 1] - v.rp[x])], 1u);
+        }
+        if (lane == 0) {
+          vis[w] |= nw;
+          cnt += (uint32_t)__popcll(nw);
+        }
+      }
+      if (lane == 0) {
+        front[w] = nw;
+        nxt[w] = 0ull;
+      }
+    }
+    if (lane == 0 && cnt)
+      (void)__hip_atomic_fetch_add(&s_new[L % 3], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __syncthreads();
+    nn = s_new[L % 3];
+    reached += nn;
+    if (v.stats && tid == 0 && L + 1 < kMaxStatLevels) v.lvl_frontier[L + 1] = (int64_t)nn;
+    if (nn == 0 || L + 1 >= max_levels) break;
+  }
+  if (lane == 0 && edges)
+    (void)__hip_atomic_fetch_add(&s_edges, (unsigned long long)edges, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+  __syncthreads();
+  if (tid == 0) {
+    Ctl *c = v.ctl;
+    c->levels = L + 1;
+    c->reached = reached;
+    c->edges = s_edges;
+    if (nn != 0) c->err |= 2;
+  }
+}
+
+}  // namespace
+
+// Dynamic LDS of the one-workgroup traversal of a graph with `words` bitmap words.
+size_t cu_lds_bytes(int64_t words) { return (size_t)words * 3 * sizeof(uint64_t); }
+
+// Whether the one-workgroup traversal can run graph g (whole graph, m below
+// 2^25, bitmaps within max_lds bytes of LDS next to the static LDS).
+bool cu_fits(int64_t n, int64_t m, bool whole, int max_lds) {
+  const int64_t words = (n + 63) / 64;
+  return whole && n > 0 && m < (1ll << 25) && (int64_t)cu_lds_bytes(words) + 1024 <= max_lds;
+}
+
+hipError_t launch_bfs_cu(const View &v, int64_t src, int max_levels, hipStream_t s) {
+  const size_t lds = cu_lds_bytes(v.words);
+  (void)hipFuncSetAttribute((const void *)k_bfs_cu, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_bfs_cu, dim3(1), dim3(kCuBlock), lds, s, v, src, max_levels);
+  return hipGetLastError();
+}
+
+}  // namespace bfsk

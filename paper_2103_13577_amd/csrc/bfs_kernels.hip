@@ -134,7 +134,8 @@ struct SparseAcc {
 // All lanes of the wavefront must call this (the appends use ballots).
 template <int K>
 __device__ __forceinline__ void probe_batch_sparse(const View &v, const int32_t (&u)[K],
-                                                   const bool (&ok)[K], int L, SparseAcc &acc) {
+                                                   const bool (&ok)[K], int L, SparseAcc &acc,
+                                                   int32_t *dist) {
   const int nxt = (L + 1) % kRing;
   const int lane = lane_id();
   uint64_t vis[K];
@@ -154,7 +155,7 @@ __device__ __forceinline__ void probe_batch_sparse(const View &v, const int32_t 
     bool own = false;
     if (win[j]) {
       const int64_t x = u[j];
-      v.dist[v.old_id ? (int64_t)v.old_id[x] : x] = L + 1;
+      dist[v.old_id ? (int64_t)v.old_id[x] : x] = L + 1;
       acc.nnew += 1;
       own = x >= v.vb && x < v.ve;
       if (own) {
@@ -200,8 +201,8 @@ constexpr int kUnrollSmall = 8;  // edges per lane in flight (lane-group tier)
 template <bool SPARSE, int K>
 __device__ __forceinline__ void probe_dispatch(const View &v, const int32_t (&u)[K],
                                                const bool (&ok)[K], int L, SparseAcc &acc,
-                                               HotCache hot) {
-  if (SPARSE) probe_batch_sparse<K>(v, u, ok, L, acc);
+                                               HotCache hot, int32_t *dist) {
+  if (SPARSE) probe_batch_sparse<K>(v, u, ok, L, acc, dist);
   else probe_batch<K>(v, u, ok, hot);
 }
 
@@ -219,16 +220,17 @@ __device__ __forceinline__ uint32_t upper_slot(const uint32_t *a, uint32_t n, ui
 // first clears the counters of the ring slot two levels ahead (read at level
 // L-1, not written before level L+1). Every loop below runs the same number
 // of iterations on all lanes of a wavefront (queue-only levels use ballots).
-template <bool SPARSE>
-__device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t nvb,
-                             HotCache hot = HotCache{nullptr, 0}) {
+template <bool SPARSE, int BLOCK = kBlock>
+__device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int level, uint32_t vb_id,
+                                             uint32_t nvb, HotCache hot = HotCache{nullptr, 0}) {
+  constexpr int kWaves = BLOCK / kWave;
   __shared__ int64_t s_lo, s_hi;
-  __shared__ uint64_t s_acc[3][kWavesPerBlock];
+  __shared__ uint64_t s_acc[3][kWaves];
   const int cur = level % kRing;
   const int lane = lane_id();
   const uint32_t wave = threadIdx.x / kWave;
-  const uint64_t gwave = (uint64_t)vb_id * kWavesPerBlock + wave;
-  const uint64_t nwaves = (uint64_t)nvb * kWavesPerBlock;
+  const uint64_t gwave = (uint64_t)vb_id * kWaves + wave;
+  const uint64_t nwaves = (uint64_t)nvb * kWaves;
   SparseAcc acc;
 
   if (vb_id == 0 && threadIdx.x == 0) {
@@ -256,16 +258,16 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
     }
     __syncthreads();
     const int64_t lo = s_lo, hi = s_hi;
-    for (int64_t e0 = lo; e0 < hi; e0 += kBlock * kUnroll) {
+    for (int64_t e0 = lo; e0 < hi; e0 += BLOCK * kUnroll) {
       int32_t u[kUnroll];
       bool ok[kUnroll];
 #pragma unroll
       for (int j = 0; j < kUnroll; ++j) {
-        const int64_t e = e0 + (int64_t)j * kBlock + threadIdx.x;
+        const int64_t e = e0 + (int64_t)j * BLOCK + threadIdx.x;
         ok[j] = e < hi;
         u[j] = ok[j] ? load_col(v.col, e) : 0;
       }
-      probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc, hot);
+      probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc, hot, dist);
     }
     __syncthreads();
   }
@@ -284,43 +286,44 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
         ok[j] = k < e;
         u[j] = ok[j] ? load_col(v.col, k) : 0;
       }
-      probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc, hot);
+      probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc, hot, dist);
     }
   }
 
   // Tier 0: 64 vertices per wavefront, their edges dealt evenly to the lanes.
+  // Tier-0 degrees are below 2^23 (small_bin <= 24), so the wavefront's edge
+  // prefix sums fit in 32 bits and each search step is one 32-bit shuffle.
   const uint32_t n0 = load_relaxed32(&v.ctl->qn[cur][0]);
   for (uint64_t base = gwave * kWave; base < n0; base += nwaves * kWave) {
     const uint64_t i = base + lane;
-    int64_t start = 0, deg = 0;
+    int64_t start = 0;
+    int32_t deg = 0;
     if (i < n0) {
       const int64_t li = v.q0[cur][i] - v.vb;
       start = v.rp[li];
-      deg = v.rp[li + 1] - start;
+      deg = (int32_t)(v.rp[li + 1] - start);
     }
-    const int64_t incl = wave_incl_scan(deg);
-    const int64_t total = shfl64(incl, kWave - 1);
-    const int64_t excl = incl - deg;
-    // edge e of the wavefront's batch belongs to the first lane k with incl[k] > e
-    for (int64_t e0 = 0; e0 < total; e0 += kWave * kUnrollSmall) {
+    const int32_t incl = wave_incl_scan32(deg);
+    const int32_t total = __shfl(incl, kWave - 1);
+    // edge e of the batch is edge (e - excl[k]) of lane k's vertex, k the first
+    // lane with incl[k] > e: its column index is col[start[k] - excl[k] + e]
+    const int64_t rebase = start - (int64_t)(incl - deg);
+    for (int32_t e0 = 0; e0 < total; e0 += kWave * kUnrollSmall) {
       int32_t u[kUnrollSmall];
       bool ok[kUnrollSmall];
 #pragma unroll
       for (int j = 0; j < kUnrollSmall; ++j) {
-        const int64_t e = e0 + (int64_t)j * kWave + lane;
+        const int32_t e = e0 + j * kWave + lane;
         int k = 0;
 #pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-          const int64_t val = shfl64(incl, k + step - 1);
-          if (val <= e) k += step;
-        }
+        for (int step = 32; step >= 1; step >>= 1)
+          if (__shfl(incl, k + step - 1) <= e) k += step;
         k = min(k, kWave - 1);
-        const int64_t xk = shfl64(excl, k);
-        const int64_t sk = shfl64(start, k);
+        const int64_t rk = shfl64(rebase, k);
         ok[j] = e < total;
-        u[j] = ok[j] ? load_col(v.col, sk + (e - xk)) : 0;
+        u[j] = ok[j] ? load_col(v.col, rk + e) : 0;
       }
-      probe_dispatch<SPARSE, kUnrollSmall>(v, u, ok, level, acc, hot);
+      probe_dispatch<SPARSE, kUnrollSmall>(v, u, ok, level, acc, hot, dist);
     }
   }
 
@@ -337,7 +340,7 @@ __device__ void expand_phase(const View &v, int level, uint32_t vb_id, uint32_t 
     __syncthreads();
     if (threadIdx.x == 0) {
       uint64_t ta = 0, tb = 0, tc = 0;
-      for (int w = 0; w < kWavesPerBlock; ++w) {
+      for (int w = 0; w < kWaves; ++w) {
         ta += s_acc[0][w];
         tb += s_acc[1][w];
         tc += s_acc[2][w];
@@ -366,7 +369,8 @@ __device__ __forceinline__ uint64_t owned_mask(int64_t w, int64_t vb, int64_t ve
   return m;
 }
 
-__device__ void merge_phase(const View &v, const MergeArgs &a, uint32_t vb_id, uint32_t nvb) {
+__device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const MergeArgs &a,
+                                            uint32_t vb_id, uint32_t nvb) {
   __shared__ uint32_t s_cnt[kWavesPerBlock][3];
   __shared__ uint64_t s_chunks[kWavesPerBlock];
   __shared__ uint32_t s_base[3];
@@ -434,7 +438,7 @@ __device__ void merge_phase(const View &v, const MergeArgs &a, uint32_t vb_id, u
           const uint64_t wj = readlane64(nw, js[q]);
           const uint64_t oj = readlane64(om, js[q]);
           const int64_t vtx = (wbase + js[q]) * 64 + lane;
-          if ((wj >> lane) & 1ull) v.dist[v.old_id ? (int64_t)v.old_id[vtx] : vtx] = dnew;
+          if ((wj >> lane) & 1ull) dist[v.old_id ? (int64_t)v.old_id[vtx] : vtx] = dnew;
           own[q] = (oj >> lane) & 1ull;
           if (own[q]) {
             const int64_t li = vtx - v.vb;
@@ -580,9 +584,10 @@ __device__ void merge_phase(const View &v, const MergeArgs &a, uint32_t vb_id, u
 // ---------------------------------------------------------------------------
 
 // Loads visited words [0, words) into this block's LDS copy.
+template <int BLOCK = kBlock>
 __device__ __forceinline__ HotCache load_hot(const View &v, uint64_t *lds, uint32_t words) {
   words = (uint32_t)min<int64_t>(words, v.words);
-  for (uint32_t i = threadIdx.x; i < words; i += kBlock) lds[i] = v.visited[i];
+  for (uint32_t i = threadIdx.x; i < words; i += BLOCK) lds[i] = v.visited[i];
   __syncthreads();
   return HotCache{lds, words};
 }
@@ -591,12 +596,24 @@ __device__ __forceinline__ HotCache load_hot(const View &v, uint64_t *lds, uint3
 // (the launch must provide hot_words * 8 bytes of dynamic LDS).
 __global__ void __launch_bounds__(kBlock) k_expand(View v, int level, uint32_t hot_words) {
   extern __shared__ uint64_t s_hot[];
-  if (hot_words) expand_phase<false>(v, level, blockIdx.x, gridDim.x, load_hot(v, s_hot, hot_words));
-  else expand_phase<false>(v, level, blockIdx.x, gridDim.x);
+  if (hot_words)
+    expand_phase<false>(v, v.dist, level, blockIdx.x, gridDim.x, load_hot(v, s_hot, hot_words));
+  else
+    expand_phase<false>(v, v.dist, level, blockIdx.x, gridDim.x);
+}
+
+// Wide variant for large LDS copies: one 1024-thread workgroup per CU shares
+// up to ~144 KB of hub bits (on a degree-relabelled R-MAT graph the first 16K
+// words hold the targets of most edges), instead of four 256-thread blocks
+// each holding a small copy.
+__global__ void __launch_bounds__(kWideBlock) k_expand_wide(View v, int level, uint32_t hot_words) {
+  extern __shared__ uint64_t s_hot[];
+  expand_phase<false, kWideBlock>(v, v.dist, level, blockIdx.x, gridDim.x,
+                                  load_hot<kWideBlock>(v, s_hot, hot_words));
 }
 
 __global__ void __launch_bounds__(kBlock) k_merge(View v, MergeArgs a) {
-  merge_phase(v, a, blockIdx.x, gridDim.x);
+  merge_phase(v, v.dist, a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -613,38 +630,47 @@ __device__ __forceinline__ bool level_is_sparse(const View &v, int L) {
   return v.sparse_div > 0 && fsize * (uint64_t)v.sparse_div < (uint64_t)v.words;
 }
 
-__global__ void __launch_bounds__(kBlock) k_expand_g(View v, uint32_t hot_words) {
+// The caller's distance array of the running traversal comes from the
+// control block (the captured launches outlive any one call's pointer).
+template <int BLOCK>
+__device__ __forceinline__ void expand_g_body(const View &v, uint32_t hot_words) {
   extern __shared__ uint64_t s_hot[];
   if (load_relaxed_i32(&v.ctl->gdone)) return;
   const int L = load_relaxed_i32(&v.ctl->glevel);
-  View w = v;
-  w.dist = v.ctl->gdist;
-  if (level_is_sparse(w, L)) {
-    expand_phase<true>(w, L, blockIdx.x, gridDim.x);
+  int32_t *dist = v.ctl->gdist;
+  if (level_is_sparse(v, L)) {
+    expand_phase<true, BLOCK>(v, dist, L, blockIdx.x, gridDim.x);
     return;
   }
   // the LDS copy of the hub bits pays off only when the frontier is large
   const int cur = L % kRing;
-  const uint64_t fsize = (uint64_t)load_relaxed32(&w.ctl->qn[cur][0]) +
-                         load_relaxed32(&w.ctl->qn[cur][1]) +
-                         (load_relaxed64(&w.ctl->heavy[cur]) >> kHeavyShift);
-  if (hot_words && fsize * 16 >= (uint64_t)w.n)
-    expand_phase<false>(w, L, blockIdx.x, gridDim.x, load_hot(w, s_hot, hot_words));
+  const uint64_t fsize = (uint64_t)load_relaxed32(&v.ctl->qn[cur][0]) +
+                         load_relaxed32(&v.ctl->qn[cur][1]) +
+                         (load_relaxed64(&v.ctl->heavy[cur]) >> kHeavyShift);
+  if (hot_words && fsize * 16 >= (uint64_t)v.n)
+    expand_phase<false, BLOCK>(v, dist, L, blockIdx.x, gridDim.x,
+                               load_hot<BLOCK>(v, s_hot, hot_words));
   else
-    expand_phase<false>(w, L, blockIdx.x, gridDim.x);
+    expand_phase<false, BLOCK>(v, dist, L, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_expand_g(View v, uint32_t hot_words) {
+  expand_g_body<kBlock>(v, hot_words);
+}
+
+__global__ void __launch_bounds__(kWideBlock) k_expand_gw(View v, uint32_t hot_words) {
+  expand_g_body<kWideBlock>(v, hot_words);
 }
 
 __global__ void __launch_bounds__(kBlock) k_merge_g(View v) {
   if (load_relaxed_i32(&v.ctl->gdone)) return;
   const int L = load_relaxed_i32(&v.ctl->glevel);
   if (level_is_sparse(v, L)) return;  // a queue-only level has nothing to merge
-  View w = v;
-  w.dist = v.ctl->gdist;
-  MergeArgs a{};
+  MergeArgs a;
   a.k = 0;
   a.keep_next = 0;
   a.level = L;
-  merge_phase(w, a, blockIdx.x, gridDim.x);
+  merge_phase(v, v.ctl->gdist, a, blockIdx.x, gridDim.x);
 }
 
 // One thread: termination test and level advance; clears the histogram row
@@ -668,7 +694,10 @@ __global__ void k_advance_g(View v, int max_levels) {
 hipError_t enqueue_graph_levels(const View &v, int levels, int max_levels, int expand_grid,
                                 int merge_grid, uint32_t hot_words, hipStream_t s) {
   for (int i = 0; i < levels; ++i) {
-    hipLaunchKernelGGL(k_expand_g, dim3(expand_grid), dim3(kBlock), hot_words * 8, s, v, hot_words);
+    if (hot_words > kNarrowHotMax)
+      hipLaunchKernelGGL(k_expand_gw, dim3(expand_grid), dim3(kWideBlock), hot_words * 8, s, v, hot_words);
+    else
+      hipLaunchKernelGGL(k_expand_g, dim3(expand_grid), dim3(kBlock), hot_words * 8, s, v, hot_words);
     hipLaunchKernelGGL(k_merge_g, dim3(merge_grid), dim3(kBlock), 0, s, v);
     hipLaunchKernelGGL(k_advance_g, dim3(1), dim3(64), 0, s, v, max_levels);
   }
@@ -706,13 +735,13 @@ __device__ __forceinline__ void persistent_body(const View &v, int max_levels) {
                            (load_relaxed64(&v.ctl->heavy[cur]) >> kHeavyShift);
     const bool sparse = v.sparse_div > 0 && fsize * (uint64_t)v.sparse_div < (uint64_t)v.words;
     if (sparse) {
-      expand_phase<true>(v, L, blockIdx.x, nb);
+      expand_phase<true>(v, v.dist, L, blockIdx.x, nb);
       grid_barrier(&v.ctl->bar, nb);
     } else {
-      expand_phase<false>(v, L, blockIdx.x, nb);
+      expand_phase<false>(v, v.dist, L, blockIdx.x, nb);
       grid_barrier(&v.ctl->bar, nb);
       a.level = L;
-      merge_phase(v, a, blockIdx.x, nb);
+      merge_phase(v, v.dist, a, blockIdx.x, nb);
       grid_barrier(&v.ctl->bar, nb);
     }
     const uint64_t nn = load_relaxed64(&v.ctl->newcnt[L % 3]);
@@ -785,7 +814,10 @@ hipError_t launch_reset(const View &v, int64_t src, int grid, hipStream_t s) {
 }
 
 hipError_t launch_expand(const View &v, int level, int grid, uint32_t hot_words, hipStream_t s) {
-  hipLaunchKernelGGL(k_expand, dim3(grid), dim3(kBlock), hot_words * 8, s, v, level, hot_words);
+  if (hot_words > kNarrowHotMax)
+    hipLaunchKernelGGL(k_expand_wide, dim3(grid), dim3(kWideBlock), hot_words * 8, s, v, level, hot_words);
+  else
+    hipLaunchKernelGGL(k_expand, dim3(grid), dim3(kBlock), hot_words * 8, s, v, level, hot_words);
   return hipGetLastError();
 }
 
@@ -804,13 +836,22 @@ hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, 
   return hipGetLastError();
 }
 
-// Co-resident blocks per CU of the per-phase expansion kernel with the given
-// dynamic LDS bytes.
-int expand_blocks_per_cu(size_t lds_bytes) {
+// Co-resident blocks per CU of the per-phase expansion kernel that an LDS
+// copy of hot_words visited words selects (the wide kernel above
+// kNarrowHotMax words). Raises the wide kernels' dynamic-LDS limit first.
+int expand_blocks_per_cu(uint32_t hot_words) {
+  const size_t lds = (size_t)hot_words * 8;
   int nb = 0;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_expand, kBlock, lds_bytes) == hipSuccess
-             ? nb
-             : 0;
+  if (hot_words > kNarrowHotMax) {
+    (void)hipFuncSetAttribute((const void *)k_expand_wide,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void *)k_expand_gw,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_expand_wide, kWideBlock, lds) == hipSuccess
+               ? nb
+               : 0;
+  }
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_expand, kBlock, lds) == hipSuccess ? nb : 0;
 }
 
 // Co-resident blocks per CU for the persistent kernel (variant 0 or 1).

@@ -44,6 +44,16 @@ __device__ __forceinline__ int64_t wave_incl_scan(int64_t x) {
   return x;
 }
 
+__device__ __forceinline__ int32_t wave_incl_scan32(int32_t x) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int32_t y = __shfl(x, l >= d ? l - d : l);
+    if (l >= d) x += y;
+  }
+  return x;
+}
+
 __device__ __forceinline__ int64_t wave_sum(int64_t x) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) x += shfl64(x, lane_id() ^ d);

@@ -141,7 +141,8 @@ __device__ void ms_push_phase(const MsView &v, int L, uint32_t vb_id, uint32_t n
   const uint32_t n0 = load_relaxed32(&v.ctl->qn[cur][0]);
   for (uint64_t base = gwave * kWave; base < n0; base += nwaves * kWave) {
     const uint64_t i = base + lane;
-    int64_t start = 0, deg = 0;
+    int64_t start = 0;
+    int32_t deg = 0;  // tier-0 degrees are below 2^23 (small_bin <= 24)
     bool sp = false;
     uint64_t f[LW];
 #pragma unroll
@@ -149,7 +150,7 @@ __device__ void ms_push_phase(const MsView &v, int L, uint32_t vb_id, uint32_t n
     if (i < n0) {
       const int64_t x = v.q0[cur][i];
       start = v.rp[x];
-      deg = v.rp[x + 1] - start;
+      deg = (int32_t)(v.rp[x + 1] - start);
       sp = (sparse_mask >> ms_graph_of(v, x, s_off)) & 1u;
 #pragma unroll
       for (int l = 0; l < LW; ++l) f[l] = v.F[x * LW + l];
@@ -158,26 +159,25 @@ __device__ void ms_push_phase(const MsView &v, int L, uint32_t vb_id, uint32_t n
         for (int l = 0; l < LW; ++l)
           if (f[l]) v.F[x * LW + l] = 0;
     }
-    const int64_t incl = wave_incl_scan(deg);
-    const int64_t total = shfl64(incl, kWave - 1);
-    const int64_t excl = incl - deg;
+    const int32_t incl = wave_incl_scan32(deg);
+    const int32_t total = __shfl(incl, kWave - 1);
+    // edge e belongs to the first lane k with incl[k] > e; its column index is
+    // col[start[k] - excl[k] + e]
+    const int64_t rebase = start - (int64_t)(incl - deg);
     const int spi = sp ? 1 : 0;
-    for (int64_t e0 = 0; e0 < total; e0 += kWave) {
-      const int64_t e = e0 + lane;
+    for (int32_t e0 = 0; e0 < total; e0 += kWave) {
+      const int32_t e = e0 + lane;
       int k = 0;
 #pragma unroll
-      for (int step = 32; step >= 1; step >>= 1) {
-        const int64_t val = shfl64(incl, k + step - 1);
-        if (val <= e) k += step;
-      }
+      for (int step = 32; step >= 1; step >>= 1)
+        if (__shfl(incl, k + step - 1) <= e) k += step;
       k = min(k, kWave - 1);
-      const int64_t xk = shfl64(excl, k);
-      const int64_t sk = shfl64(start, k);
+      const int64_t rk = shfl64(rebase, k);
       const bool spk = __shfl(spi, k) != 0;
       uint64_t fk[LW];
 #pragma unroll
       for (int l = 0; l < LW; ++l) fk[l] = (uint64_t)shfl64((int64_t)f[l], k);
-      if (e < total) ms_push_edge<LW>(v, __builtin_nontemporal_load(v.col + sk + (e - xk)), fk, spk, L);
+      if (e < total) ms_push_edge<LW>(v, __builtin_nontemporal_load(v.col + rk + e), fk, spk, L);
     }
   }
 }

@@ -127,13 +127,15 @@ bfs_status choose_tuning(Plan *p) {
     if (p->opt.small_bin > 0) t.small_bin = p->opt.small_bin;
     if (p->opt.wave_bin > 0) t.wave_bin = p->opt.wave_bin;
     if (p->opt.hot_words > 0) t.hot_words = p->opt.hot_words;
-    if (t.hot_words > 16384) return p->fail(BFS_ERR_ARG, "hot_words above 16384 (128 KB of LDS)");
+    // the kernels' static LDS needs under 1 KB next to the hub copy
+    if ((int64_t)t.hot_words * 8 + 1024 > p->max_lds)
+      return p->fail(BFS_ERR_ARG, "hot_words exceeds the LDS one workgroup may use");
     if (p->opt.chunk_edges > 0) {
       int s = 0;
       while ((1 << s) < p->opt.chunk_edges && s < 30) ++s;
       t.chunk_shift = s;
     }
-    if (t.small_bin < 1 || t.wave_bin < t.small_bin || t.chunk_shift < 6)
+    if (t.small_bin < 1 || t.small_bin > 24 || t.wave_bin < t.small_bin || t.chunk_shift < 6)
       return p->fail(BFS_ERR_ARG, "bad tier thresholds");
     // untuned default: the cooperative loop with the 64-VGPR budget, one
     // block per 16K edges and vertices of the share (a small grid keeps the
@@ -147,6 +149,11 @@ bfs_status choose_tuning(Plan *p) {
     t.persist_grid = (int)std::max<int64_t>(
         1, std::min<int64_t>(max_grid, std::max<int64_t>(work_grid, p->num_cus / 4)));
     t.loop_mode = (p->coop && per_cu > 0) ? BFS_LOOP_PERSISTENT : BFS_LOOP_HOST;
+    // small whole graphs: one workgroup with the bitmaps in LDS
+    const bfs_graph &gr = p->graphs[i];
+    if (cu_fits(gr.n_global, m, gr.v_begin == 0 && gr.v_end == gr.n_global, p->max_lds) &&
+        !p->opt.exchange)
+      t.loop_mode = BFS_LOOP_CU;
     // cstart entries are 32-bit: total chunks must stay below 2^32.
     if ((m >> t.chunk_shift) + (p->graphs[i].v_end - p->graphs[i].v_begin) >= (1ll << 32))
       return p->fail(BFS_ERR_ARG, "chunk_edges too small for this graph");

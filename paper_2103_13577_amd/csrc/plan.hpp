@@ -68,7 +68,9 @@ struct bfs_plan_s {
   int persist_grid = 0;  // caller's grid_blocks (0: per-graph choice)
   int bpc[2] = {0, 0};   // co-resident blocks per CU of the two persistent variants
   int bpc_expand = 0;    // co-resident blocks per CU of the per-phase expansion
-  int expand_grid(int hot_words) const;
+  std::map<int, int> hot_bpc;  // co-resident expansion blocks per CU by LDS hub-copy size
+  int max_lds = 65536;          // dynamic LDS bytes one workgroup may use
+  int expand_grid(int hot_words);
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   static constexpr int kTimedLevels = 64;
   hipEvent_t lev[kTimedLevels][3] = {};  // per level: before expand, after expand, after merge

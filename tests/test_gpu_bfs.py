@@ -52,6 +52,11 @@ MODES = [dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST),
          # LDS copy of the hubs' visited bits on large levels
          dict(loop_mode=pkg.LOOP_HOST, hot_words=64),
          dict(loop_mode=pkg.LOOP_GRAPH, hot_words=2048, small_bin=9),
+         # the 1024-thread expansion that shares a large hub copy per CU
+         dict(loop_mode=pkg.LOOP_HOST, hot_words=8192, small_bin=2, wave_bin=4, chunk_edges=64),
+         dict(loop_mode=pkg.LOOP_GRAPH, hot_words=16384),
+         # one workgroup with the bitmaps in LDS (small whole graphs)
+         dict(loop_mode=pkg.LOOP_CU), dict(loop_mode=pkg.LOOP_CU, relabel=-1),
          dict(loop_mode=pkg.LOOP_GRAPH, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64)]
 
 
@@ -297,6 +302,18 @@ def test_error_paths(gpu):
         plan.run(1, 0)
     assert e.value.status == 1
     s = int(gg.pick_sources(g, 1, seed=3)[0])
+    with pytest.raises(pkg.BfsError) as e:  # an LDS hub copy larger than a workgroup's LDS
+        pkg.Plan([dg], hot_words=1 << 20)
+    assert e.value.status == 1
+    with pytest.raises(pkg.BfsError) as e:  # unknown level loop
+        pkg.Plan([dg], loop_mode=9)
+    assert e.value.status == 1
+    big = gg.empty_graph(1 << 20)  # bitmaps of 2^20 bits do not fit one workgroup's LDS
+    bplan = pkg.Plan([pkg.DeviceGraph.from_csr(big, gpu)], loop_mode=pkg.LOOP_CU)
+    with pytest.raises(pkg.BfsError) as e:
+        bplan.run(0, 5)
+    assert e.value.status == 1
+    bplan.close()
     d, _, _ = plan.run(0, s)  # still usable after errors
     assert np.array_equal(d.cpu().numpy(), oracle.bfs(g, s))
     plan.close()
