@@ -167,7 +167,7 @@ bfs_status autotune_graphs(Plan *p) {
       }
     t = best;
     if (p->opt.chunk_edges <= 0)
-      for (int cs : {11, 13}) {
+      for (int cs : {10, 12}) {
         Tuning c = best;
         c.chunk_shift = cs;
         if ((s = trial(c))) return s;

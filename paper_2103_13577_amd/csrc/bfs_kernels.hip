@@ -11,8 +11,8 @@
 //               tier 0: small degrees, 64 vertices per wavefront with their
 //                       edges spread evenly over the lanes;
 //               tier 1: medium degrees, one wavefront per vertex;
-//               tier 2: large degrees, fixed-size edge chunks, one workgroup
-//                       per chunk (a hub is spread over many workgroups).
+//               tier 2: large degrees, fixed-size edge chunks, one wavefront
+//                       per chunk (a hub is spread over many CUs).
 //   merge   - Phase 2: OR of the local bitmap with k received bitmaps,
 //             new = merged & ~visited, distance level+1 for every new vertex,
 //             owned new vertices compacted (ballot/popcount) straight into
@@ -206,16 +206,6 @@ __device__ __forceinline__ void probe_dispatch(const View &v, const int32_t (&u)
   else probe_batch<K>(v, u, ok, hot);
 }
 
-// Largest s in [0, n) with a[s] <= key (a ascending, a[0] == 0 <= key).
-__device__ __forceinline__ uint32_t upper_slot(const uint32_t *a, uint32_t n, uint64_t key) {
-  uint32_t lo = 0, hi = n - 1;
-  while (lo < hi) {
-    uint32_t mid = (lo + hi + 1) >> 1;
-    if ((uint64_t)a[mid] <= key) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 // Expansion of level `level` by virtual block `vb_id` of `nvb` blocks. Block 0
 // first clears the counters of the ring slot two levels ahead (read at level
 // L-1, not written before level L+1). Every loop below runs the same number
@@ -224,7 +214,6 @@ template <bool SPARSE, int BLOCK = kBlock>
 __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int level, uint32_t vb_id,
                                              uint32_t nvb, HotCache hot = HotCache{nullptr, 0}) {
   constexpr int kWaves = BLOCK / kWave;
-  __shared__ int64_t s_lo, s_hi;
   __shared__ uint64_t s_acc[3][kWaves];
   const int cur = level % kRing;
   const int lane = lane_id();
@@ -242,34 +231,29 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     v.ctl->ownedcnt[(level + 1) % 3] = 0;
   }
 
-  // Tier 2: fixed-size edge chunks of heavy vertices, one workgroup each.
+  // Tier 2: heavy vertices cut into fixed-size edge chunks, one wavefront per
+  // chunk; the wavefront finds the chunk's vertex with a 64-way search of the
+  // chunk starts.
   const uint64_t hv = load_relaxed64(&v.ctl->heavy[cur]);
   const uint32_t n2 = (uint32_t)(hv >> kHeavyShift);
   const uint64_t nch = hv & kChunkMask;
-  for (uint64_t c = vb_id; c < nch; c += nvb) {
-    if (threadIdx.x == 0) {
-      const uint32_t s = upper_slot(v.cstart[cur], n2, c);
-      const int32_t x = v.q2[cur][s];
-      const int64_t li = x - v.vb;
-      const int64_t b = v.rp[li], e = v.rp[li + 1];
-      const int64_t lo = b + ((int64_t)(c - v.cstart[cur][s]) << v.chunk_shift);
-      s_lo = lo;
-      s_hi = min(e, lo + (1ll << v.chunk_shift));
-    }
-    __syncthreads();
-    const int64_t lo = s_lo, hi = s_hi;
-    for (int64_t e0 = lo; e0 < hi; e0 += BLOCK * kUnroll) {
+  for (uint64_t c = gwave; c < nch; c += nwaves) {
+    const uint32_t s = wave_upper_slot(v.cstart[cur], n2, c);
+    const int64_t li = v.q2[cur][s] - v.vb;
+    const int64_t b = v.rp[li], e = v.rp[li + 1];
+    const int64_t lo = b + ((int64_t)(c - v.cstart[cur][s]) << v.chunk_shift);
+    const int64_t hi = min(e, lo + (1ll << v.chunk_shift));
+    for (int64_t e0 = lo; e0 < hi; e0 += kWave * kUnroll) {
       int32_t u[kUnroll];
       bool ok[kUnroll];
 #pragma unroll
       for (int j = 0; j < kUnroll; ++j) {
-        const int64_t e = e0 + (int64_t)j * BLOCK + threadIdx.x;
-        ok[j] = e < hi;
-        u[j] = ok[j] ? load_col(v.col, e) : 0;
+        const int64_t k = e0 + (int64_t)j * kWave + lane;
+        ok[j] = k < hi;
+        u[j] = ok[j] ? load_col(v.col, k) : 0;
       }
       probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc, hot, dist);
     }
-    __syncthreads();
   }
 
   // Tier 1: one wavefront per vertex.

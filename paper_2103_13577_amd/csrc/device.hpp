@@ -66,6 +66,26 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
   return x;
 }
 
+// Largest s in [0, n) with a[s] <= key (a strictly ascending, a[0] == 0 <=
+// key), found by the whole wavefront: each round samples 64 evenly spaced
+// entries of the remaining range and keeps the segment after the last sample
+// <= key, so n entries take ceil(log64 n) dependent loads instead of log2 n.
+// All lanes must call it; the result is wave-uniform.
+__device__ __forceinline__ uint32_t wave_upper_slot(const uint32_t *a, uint32_t n, uint64_t key) {
+  const int lane = lane_id();
+  uint32_t lo = 0, len = n;  // the answer lies in [lo, lo + len)
+  while (len > 1) {
+    const uint32_t step = (len + kWave - 1) / kWave;
+    const uint32_t idx = lo + (uint32_t)lane * step;
+    const bool le = idx < lo + len && (uint64_t)a[idx] <= key;
+    const uint32_t cnt = (uint32_t)__popcll(ballot(le));  // >= 1: a[lo] <= key
+    const uint32_t nlo = lo + (cnt - 1) * step;
+    len = min(step, lo + len - nlo);
+    lo = nlo;
+  }
+  return lo;
+}
+
 // Relaxed device-scope atomics (agent scope: every CU of every XCD).
 __device__ __forceinline__ void atomic_or_noret(uint64_t *p, uint64_t v) {
   (void)__hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -18,15 +18,6 @@ __device__ __forceinline__ uint64_t wave_or(uint64_t x) {
   return x;
 }
 
-__device__ __forceinline__ uint32_t ms_upper_slot(const uint32_t *a, uint32_t n, uint64_t key) {
-  uint32_t lo = 0, hi = n - 1;
-  while (lo < hi) {
-    uint32_t mid = (lo + hi + 1) >> 1;
-    if ((uint64_t)a[mid] <= key) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 // Per-level mode of each graph: dense (sweep every vertex) or sparse (only
 // the vertices touched by the expansion are swept).
 struct MsModes {
@@ -79,41 +70,30 @@ __device__ __forceinline__ void ms_push_edge(const MsView &v, int64_t u, const u
 template <int LW>
 __device__ void ms_push_phase(const MsView &v, int L, uint32_t vb_id, uint32_t nvb,
                               const int64_t *s_off, uint32_t sparse_mask) {
-  __shared__ int64_t s_lo, s_hi;
-  __shared__ uint64_t s_f[LW];
-  __shared__ int32_t s_sp;
   const int cur = L & 1;
   const int lane = lane_id();
   const uint32_t wave = threadIdx.x / kWave;
   const uint64_t gwave = (uint64_t)vb_id * kWavesPerBlock + wave;
   const uint64_t nwaves = (uint64_t)nvb * kWavesPerBlock;
 
-  // Heavy vertices: fixed-size edge chunks, one workgroup each. Their
-  // frontier words are read by several workgroups and cleared in the sweep.
+  // Heavy vertices: fixed-size edge chunks, one wavefront each (a 64-way
+  // search of the chunk starts finds the vertex). Their frontier words are
+  // read by several wavefronts and cleared in the sweep.
   const uint64_t hv = load_relaxed64(&v.ctl->heavy[cur]);
   const uint32_t n2 = (uint32_t)(hv >> kHeavyShift);
   const uint64_t nch = hv & kChunkMask;
-  for (uint64_t c = vb_id; c < nch; c += nvb) {
-    if (threadIdx.x == 0) {
-      const uint32_t s = ms_upper_slot(v.cstart[cur], n2, c);
-      const int64_t x = v.q2[cur][s];
-      const int64_t b = v.rp[x], e = v.rp[x + 1];
-      const int64_t lo = b + ((int64_t)(c - v.cstart[cur][s]) << v.chunk_shift);
-      s_lo = lo;
-      s_hi = min(e, lo + (1ll << v.chunk_shift));
-#pragma unroll
-      for (int l = 0; l < LW; ++l) s_f[l] = v.F[x * LW + l];
-      s_sp = (sparse_mask >> ms_graph_of(v, x, s_off)) & 1u;
-    }
-    __syncthreads();
+  for (uint64_t c = gwave; c < nch; c += nwaves) {
+    const uint32_t s = wave_upper_slot(v.cstart[cur], n2, c);
+    const int64_t x = v.q2[cur][s];
+    const int64_t b = v.rp[x], e = v.rp[x + 1];
+    const int64_t lo = b + ((int64_t)(c - v.cstart[cur][s]) << v.chunk_shift);
+    const int64_t hi = min(e, lo + (1ll << v.chunk_shift));
     uint64_t f[LW];
 #pragma unroll
-    for (int l = 0; l < LW; ++l) f[l] = s_f[l];
-    const bool sp = s_sp != 0;
-    const int64_t lo = s_lo, hi = s_hi;
-    for (int64_t e = lo + threadIdx.x; e < hi; e += kBlock)
-      ms_push_edge<LW>(v, __builtin_nontemporal_load(v.col + e), f, sp, L);
-    __syncthreads();
+    for (int l = 0; l < LW; ++l) f[l] = v.F[x * LW + l];
+    const bool sp = (sparse_mask >> ms_graph_of(v, x, s_off)) & 1u;
+    for (int64_t k = lo + lane; k < hi; k += kWave)
+      ms_push_edge<LW>(v, __builtin_nontemporal_load(v.col + k), f, sp, L);
   }
 
   // Newly admitted sources, then medium vertices: one wavefront per vertex.

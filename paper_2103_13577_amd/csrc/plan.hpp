@@ -42,7 +42,7 @@ struct WsLayout {
 struct Tuning {
   int32_t small_bin = 6;     // degree < 32 -> lane-group tier
   int32_t wave_bin = 13;     // degree < 4096 -> wavefront tier
-  int32_t chunk_shift = 12;  // 4096-edge chunks for the workgroup tier
+  int32_t chunk_shift = 11;  // 2048-edge chunks for the hub tier (one wavefront each)
   int32_t sparse_div = 4;    // queue-only level when frontier < words / 4
   int32_t persist_variant = 0;  // 0: default registers, 1: 64-VGPR cap (8 waves/SIMD)
   int32_t persist_grid = 0;     // blocks of the cooperative launch
