@@ -59,7 +59,7 @@ class bfs_tuning(ctypes.Structure):
                 ("grid_blocks", ctypes.c_int32), ("small_bin", ctypes.c_int32),
                 ("wave_bin", ctypes.c_int32), ("chunk_edges", ctypes.c_int32),
                 ("relabelled", ctypes.c_int32), ("tuned_ms", ctypes.c_float),
-                ("hot_words", ctypes.c_int32)]
+                ("hot_words", ctypes.c_int32), ("sparse_div", ctypes.c_int32)]
 
 
 class bfs_query(ctypes.Structure):

@@ -1,8 +1,10 @@
 // Plan-time autotuner: times a few whole traversals per candidate setting on
 // the plan's own graph and keeps the fastest. Candidates: the level loop
-// (host-driven launches per phase, or the cooperative persistent loop with
-// either register budget and grid size) and the degree-bin thresholds that
-// split the frontier into the lane-group, wavefront and workgroup tiers.
+// (host-driven launches per phase, a captured graph of level steps, the
+// cooperative persistent loop with either register budget and several grid
+// sizes, or one workgroup for small graphs), the degree-bin thresholds that
+// split the frontier into the lane-group, wavefront and chunked tiers, the
+// hub chunk size, the LDS hub copy and the queue-only level threshold.
 // Settings given explicitly in the options are never changed.
 
 #include <hip/hip_runtime.h>
@@ -172,6 +174,13 @@ bfs_status autotune_graphs(Plan *p) {
         c.chunk_shift = cs;
         if ((s = trial(c))) return s;
       }
+    t = best;
+    // queue-only levels: never, or below a larger share of the bitmap sweep
+    for (int sd : {0, 16, 64}) {
+      Tuning c = best;
+      c.sparse_div = sd;
+      if ((s = trial(c))) return s;
+    }
     t = best;
     t.tuned_ms = best_ms;
   }

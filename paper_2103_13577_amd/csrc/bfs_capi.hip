@@ -353,6 +353,40 @@ bfs_status bfs_merge_frontier(bfs_plan_t p, const uint64_t *const *incoming, int
   return BFS_OK;
 }
 
+namespace {
+
+// One queue-only level of bfs_run's host-driven loop (single node, small
+// frontier): the expansion ORs straight into `visited`, writes distances and
+// fills the next level's queues, so the level needs no merge launch.
+bfs_status queue_only_level(bfs_plan_t p, int64_t *global_new) {
+  View v = p->view(p->cur_graph, p->cur_dist);
+  if (p->opt.collect_stats && p->level + 1 < kMaxStatLevels) {
+    hipError_t e = launch_clear_stats_row(v, p->level + 1, p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "stats launch");
+  }
+  const bool timed = p->time_levels && p->level < Plan::kTimedLevels;
+  if (timed) (void)hipEventRecord(p->lev[p->level][0], p->stream);
+  hipError_t e = launch_expand(v, p->level, p->wide_grid(), kQueueOnly, p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "expand launch");
+  if (timed) {
+    (void)hipEventRecord(p->lev[p->level][1], p->stream);
+    (void)hipEventRecord(p->lev[p->level][2], p->stream);
+  }
+  p->expanded_level = p->level;
+  Ctl c;
+  bfs_status st = p->read_ctl(c);
+  if (st) return st;
+  *global_new = (int64_t)c.newcnt[p->level % 3];
+  p->big_level = (int64_t)c.ownedcnt[p->level % 3] * 16 >= v.n;
+  if ((int)p->level_frontier.size() == p->level + 1)
+    p->level_frontier.push_back((int64_t)c.ownedcnt[p->level % 3]);
+  p->last_level_new = *global_new;
+  p->level += 1;
+  return BFS_OK;
+}
+
+}  // namespace
+
 bfs_status bfs_finish(bfs_plan_t p, int32_t *parent, bfs_stats *st) {
   if (!p) return BFS_ERR_ARG;
   if (!p->began) return p->fail(BFS_ERR_STATE, "bfs_finish before bfs_begin");
@@ -517,7 +551,17 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
     e = hipEventRecord(p->ev[2], p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
     p->time_levels = true;
+    const int64_t words = (g.n_global + 63) / 64;
     for (;;) {
+      // small frontiers of a single node run queue-only
+      const int64_t fr = p->level_frontier.empty() ? 0 : p->level_frontier.back();
+      if (!p->opt.exchange && tu.sparse_div > 0 && fr * tu.sparse_div < words) {
+        int64_t gnew = 0;
+        s = queue_only_level(p, &gnew);
+        if (s) { p->time_levels = false; return s; }
+        if (gnew == 0) break;
+        continue;
+      }
       const uint64_t *local_next = nullptr;
       s = bfs_expand(p, &local_next);
       if (s) { p->time_levels = false; return s; }
@@ -580,6 +624,7 @@ bfs_status bfs_plan_tuning(bfs_plan_t p, int32_t graph, bfs_tuning *out) {
   out->relabelled = (p->lay.rl_rp.size() > (size_t)graph && p->lay.rl_rp[graph]) ? 1 : 0;
   out->tuned_ms = t.tuned_ms;
   out->hot_words = t.hot_words;
+  out->sparse_div = t.sparse_div;
   return BFS_OK;
 }
 

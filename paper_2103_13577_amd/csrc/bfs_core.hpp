@@ -14,6 +14,7 @@ constexpr int kBlock = 256;    // threads per workgroup for the traversal kernel
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kWideBlock = 1024;      // threads per workgroup of the wide expansion
 constexpr uint32_t kNarrowHotMax = 4096;  // larger LDS hub copies use the wide expansion
+constexpr uint32_t kQueueOnly = 0xFFFFFFFFu;  // k_expand: run a queue-only level
 constexpr int kMaxStatLevels = 4096;
 constexpr int kHeavyShift = 40;  // packed heavy-tier counter: count << 40 | chunks
 constexpr uint64_t kChunkMask = (1ull << kHeavyShift) - 1;

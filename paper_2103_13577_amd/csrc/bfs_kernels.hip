@@ -580,7 +580,9 @@ __device__ __forceinline__ HotCache load_hot(const View &v, uint64_t *lds, uint3
 // (the launch must provide hot_words * 8 bytes of dynamic LDS).
 __global__ void __launch_bounds__(kBlock) k_expand(View v, int level, uint32_t hot_words) {
   extern __shared__ uint64_t s_hot[];
-  if (hot_words)
+  if (hot_words == kQueueOnly)
+    expand_phase<true>(v, v.dist, level, blockIdx.x, gridDim.x);
+  else if (hot_words)
     expand_phase<false>(v, v.dist, level, blockIdx.x, gridDim.x, load_hot(v, s_hot, hot_words));
   else
     expand_phase<false>(v, v.dist, level, blockIdx.x, gridDim.x);
@@ -797,8 +799,11 @@ hipError_t launch_reset(const View &v, int64_t src, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+// hot_words == kQueueOnly runs a queue-only level (no LDS copy).
 hipError_t launch_expand(const View &v, int level, int grid, uint32_t hot_words, hipStream_t s) {
-  if (hot_words > kNarrowHotMax)
+  if (hot_words == kQueueOnly)
+    hipLaunchKernelGGL(k_expand, dim3(grid), dim3(kBlock), 0, s, v, level, hot_words);
+  else if (hot_words > kNarrowHotMax)
     hipLaunchKernelGGL(k_expand_wide, dim3(grid), dim3(kWideBlock), hot_words * 8, s, v, level, hot_words);
   else
     hipLaunchKernelGGL(k_expand, dim3(grid), dim3(kBlock), hot_words * 8, s, v, level, hot_words);
