@@ -145,22 +145,27 @@ def run_single(args, name, scale, ef):
     hmean = metrics.harmonic_mean(rates)
     tuning = plan.tuning(0)
     if tuning["loop_mode"] == 1:
-        # host-driven loop: the dominant kernel is the expansion; per
-        # traversal it reads every scanned column index (4 B) and two int64
-        # row offsets per frontier vertex (16 B); its launches are timed with
-        # HIP events on the plan's stream
+        # host-driven loop: the dominant kernel is the dense expansion
+        # (k_expand). Per launch it reads the column index of every edge it
+        # scans (4 B) and two int64 row offsets per frontier vertex (16 B);
+        # the device counts both, and each launch is timed with HIP events on
+        # the plan's stream. Queue-only levels (small frontiers) run another
+        # kernel and are not part of this figure.
         kname = "k_expand"
         exp_ms = np.array([s.expand_ms for s in stats])
-        launches = np.array([max(s.expand_launches, 1) for s in stats])
-        k_bytes = 4 * edges + 16 * reached
+        launches = np.array([s.expand_launches for s in stats])
+        k_bytes = np.array([4.0 * s.dense_edges + 16.0 * s.dense_frontier for s in stats])
         achieved = float(np.sum(k_bytes) / (np.sum(exp_ms) * 1e-3) / 1e9)
-        per_launch_bytes = float(np.sum(k_bytes) / np.sum(launches))
-        avg_launch_ms = float(np.sum(exp_ms) / np.sum(launches))
+        per_launch_bytes = float(np.sum(k_bytes) / max(np.sum(launches), 1))
+        avg_launch_ms = float(np.sum(exp_ms) / max(np.sum(launches), 1))
         n_launches = int(np.sum(launches))
     else:
-        # device-resident loop: one launch per traversal, which also writes
-        # each reached vertex's distance (4 B)
-        kname = "k_persistent_occ8" if tuning["persist_variant"] == 1 else "k_persistent"
+        # device-resident loops: one launch per traversal (for the captured
+        # graph, the replayed level steps), which also writes each reached
+        # vertex's distance (4 B)
+        kname = {2: "k_persistent_occ8" if tuning["persist_variant"] == 1 else "k_persistent",
+                 3: "k_expand_g+k_merge_g (captured level steps)",
+                 4: "k_bfs_cu"}.get(tuning["loop_mode"], "unknown")
         k_bytes = 4 * edges + 16 * reached + 4 * reached
         achieved = float(np.mean(k_bytes) / (np.mean(loop_ms) * 1e-3) / 1e9)
         per_launch_bytes = float(np.mean(k_bytes))

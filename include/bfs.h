@@ -112,7 +112,8 @@ typedef struct {
                               1024-thread block per CU sharing the copy. At most (LDS bytes
                               per workgroup - 1024) / 8, else BFS_ERR_ARG; 0 = tuned,
                               -1 = none */
-  int32_t reserved;
+  int32_t sparse_div;      /* single node: a level runs queue-only (no bitmap merge) when its
+                              frontier is below ceil(n/64) / sparse_div; 0 = tuned, -1 = never */
 } bfs_options;
 
 /* Fills *o with defaults (all zero / NULL, loop_mode AUTO). */
@@ -125,10 +126,16 @@ typedef struct {
   float ms;              /* device time of the whole traversal, reset included (HIP events) */
   float loop_ms;         /* device time of the level loop alone (the persistent launch, or
                             first expansion to last merge when host-driven) */
-  float expand_ms;       /* host-driven loop: summed device time of the expansion launches
-                            of the first 64 levels (0 for the persistent loop) */
+  float expand_ms;       /* host-driven loop: summed device time of the dense expansion
+                            launches (k_expand) of the first 64 levels (0 for the other
+                            loops) */
   float merge_ms;        /* the same for the merge launches */
   int32_t expand_launches; /* launches summed in expand_ms */
+  int64_t dense_edges;     /* edges scanned by the dense (bitmap) expansions of this traversal,
+                              every level loop; with dense_frontier, the work behind expand_ms */
+  int64_t dense_frontier;  /* frontier vertices of those expansions */
+  float queue_ms;          /* host-driven loop: device time of the queue-only levels (their
+                              expansions are not in expand_ms) */
 } bfs_stats;
 
 #define BFS_MAX_LEVEL_STATS 4096

@@ -44,14 +44,16 @@ class bfs_options(ctypes.Structure):
                 ("batch_lanes", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
                 ("exchange", EXCHANGE_FN), ("exchange_ctx", ctypes.c_void_p),
                 ("relabel", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("hot_words", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("hot_words", ctypes.c_int32), ("sparse_div", ctypes.c_int32)]
 
 
 class bfs_stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("reached", ctypes.c_int64),
                 ("edges_scanned", ctypes.c_int64), ("ms", ctypes.c_float),
                 ("loop_ms", ctypes.c_float), ("expand_ms", ctypes.c_float),
-                ("merge_ms", ctypes.c_float), ("expand_launches", ctypes.c_int32)]
+                ("merge_ms", ctypes.c_float), ("expand_launches", ctypes.c_int32),
+                ("dense_edges", ctypes.c_int64), ("dense_frontier", ctypes.c_int64),
+                ("queue_ms", ctypes.c_float)]
 
 
 class bfs_tuning(ctypes.Structure):
@@ -179,7 +181,7 @@ class Plan:
 
     def __init__(self, graphs, *, loop_mode=LOOP_AUTO, small_bin=0, wave_bin=0, chunk_edges=0,
                  grid_blocks=0, batch_lanes=0, collect_stats=False, exchange=None, stream=None,
-                 relabel=0, autotune=0, hot_words=0):
+                 relabel=0, autotune=0, hot_words=0, sparse_div=0):
         torch = _torch()
         L = lib()
         if isinstance(graphs, DeviceGraph):
@@ -196,6 +198,7 @@ class Plan:
         o.relabel = int(relabel)
         o.autotune = int(autotune)
         o.hot_words = int(hot_words)
+        o.sparse_div = int(sparse_div)
         self._exchange_py = exchange
         self._exchange_keep = None
         if exchange is not None:

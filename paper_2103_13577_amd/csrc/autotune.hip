@@ -176,11 +176,12 @@ bfs_status autotune_graphs(Plan *p) {
       }
     t = best;
     // queue-only levels: never, or below a larger share of the bitmap sweep
-    for (int sd : {0, 16, 64}) {
-      Tuning c = best;
-      c.sparse_div = sd;
-      if ((s = trial(c))) return s;
-    }
+    if (p->opt.sparse_div == 0)
+      for (int sd : {0, 16, 64}) {
+        Tuning c = best;
+        c.sparse_div = sd;
+        if ((s = trial(c))) return s;
+      }
     t = best;
     t.tuned_ms = best_ms;
   }

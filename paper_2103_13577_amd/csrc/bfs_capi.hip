@@ -301,7 +301,10 @@ bfs_status bfs_expand(bfs_plan_t p, const uint64_t **local_next) {
   }
   if (p->expanded_level == p->level) return p->fail(BFS_ERR_STATE, "level already expanded");
   const bool timed = p->time_levels && p->level < Plan::kTimedLevels;
-  if (timed) (void)hipEventRecord(p->lev[p->level][0], p->stream);
+  if (timed) {
+    p->level_queue_only[p->level] = false;
+    (void)hipEventRecord(p->lev[p->level][0], p->stream);
+  }
   // The LDS copy of the hub bits pays off only on large dense levels.
   const int hot = (p->cur_relabel && p->big_level) ? p->tune[p->cur_graph].hot_words : 0;
   hipError_t e = launch_expand(v, p->level, p->expand_grid(hot), hot, p->stream);
@@ -365,7 +368,10 @@ bfs_status queue_only_level(bfs_plan_t p, int64_t *global_new) {
     if (e != hipSuccess) return p->hip_fail(e, "stats launch");
   }
   const bool timed = p->time_levels && p->level < Plan::kTimedLevels;
-  if (timed) (void)hipEventRecord(p->lev[p->level][0], p->stream);
+  if (timed) {
+    p->level_queue_only[p->level] = true;
+    (void)hipEventRecord(p->lev[p->level][0], p->stream);
+  }
   hipError_t e = launch_expand(v, p->level, p->wide_grid(), kQueueOnly, p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "expand launch");
   if (timed) {
@@ -408,6 +414,9 @@ bfs_status bfs_finish(bfs_plan_t p, int32_t *parent, bfs_stats *st) {
     st->expand_ms = p->last_expand_ms;
     st->merge_ms = p->last_merge_ms;
     st->expand_launches = p->last_expand_launches;
+    st->dense_edges = (int64_t)c.xedges;
+    st->dense_frontier = (int64_t)c.xfront;
+    st->queue_ms = p->last_queue_ms;
   }
   return BFS_OK;
 }
@@ -466,7 +475,7 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   p->persistent_levels = 0;
   p->last_ms = 0.f;
   p->last_loop_ms = 0.f;
-  p->last_expand_ms = p->last_merge_ms = 0.f;
+  p->last_expand_ms = p->last_merge_ms = p->last_queue_ms = 0.f;
   p->last_expand_launches = 0;
   e = hipEventRecord(ev0, p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
@@ -596,16 +605,21 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   if (hipEventElapsedTime(&lms, p->ev[2], ev1) != hipSuccess) lms = -1.f;
   p->last_ms = ms;
   p->last_loop_ms = lms;
-  p->last_expand_ms = p->last_merge_ms = 0.f;
+  p->last_expand_ms = p->last_merge_ms = p->last_queue_ms = 0.f;
   p->last_expand_launches = 0;
   if (host_loop) {
     const int nl = std::min(p->level, Plan::kTimedLevels);
     for (int L = 0; L < nl; ++L) {
       float a = 0.f, b = 0.f;
-      if (hipEventElapsedTime(&a, p->lev[L][0], p->lev[L][1]) == hipSuccess) p->last_expand_ms += a;
+      if (hipEventElapsedTime(&a, p->lev[L][0], p->lev[L][1]) != hipSuccess) a = 0.f;
+      if (p->level_queue_only[L]) {
+        p->last_queue_ms += a;
+        continue;
+      }
+      p->last_expand_ms += a;
+      p->last_expand_launches += 1;
       if (hipEventElapsedTime(&b, p->lev[L][1], p->lev[L][2]) == hipSuccess) p->last_merge_ms += b;
     }
-    p->last_expand_launches = nl;
   }
   return bfs_finish(p, parent, st);
 }

@@ -35,7 +35,8 @@ struct Ctl {
   int32_t glevel;         // graph-launched loop: level the next captured step runs
   int32_t gdone;          // graph-launched loop: traversal finished
   int32_t *gdist;         // graph-launched loop: caller's distance array
-  uint64_t pad[1];
+  uint64_t xedges;        // edges scanned by dense (bitmap) expansions
+  uint64_t xfront;        // frontier vertices of dense expansions
 };
 
 // Kernel view of a plan's workspace for one graph.

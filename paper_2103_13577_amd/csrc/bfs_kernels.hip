@@ -58,6 +58,8 @@ __global__ void __launch_bounds__(kBlock) k_reset(View v, int64_t src_caller) {
     c->glevel = 0;
     c->gdone = 0;
     c->gdist = v.dist;
+    c->xedges = 0;
+    c->xfront = 0;
     const bool owned = src >= v.vb && src < v.ve;
     int64_t deg = 0;
     if (owned) {
@@ -97,8 +99,11 @@ __device__ __forceinline__ int32_t load_col(const int32_t *col, int64_t e) {
 
 // K independent probes: all visited words are requested before any is
 // tested, then all next words, so each lane keeps K random loads in flight.
-// Copy of the first `words` visited words in LDS (the hubs' bits once the
-// graph is relabelled by degree); words == 0 disables it.
+// The probes read and OR 32-bit halves of the 64-bit bitmap words (bit v is
+// bit v & 31 of 32-bit word v >> 5), which halves the registers a probe
+// holds. `hot` is a copy of the first `words` 64-bit visited words in LDS
+// (the hubs' bits once the graph is relabelled by degree); words == 0
+// disables it.
 struct HotCache {
   const uint64_t *lds;
   uint32_t words;
@@ -107,20 +112,24 @@ struct HotCache {
 template <int K>
 __device__ __forceinline__ void probe_batch(const View &v, const int32_t (&u)[K],
                                             const bool (&ok)[K], HotCache hot) {
-  uint64_t vis[K], nx[K];
+  const uint32_t *vis32 = reinterpret_cast<const uint32_t *>(v.visited);
+  uint32_t *next32 = reinterpret_cast<uint32_t *>(v.next);
+  const uint32_t *hot32 = reinterpret_cast<const uint32_t *>(hot.lds);
+  const uint32_t hot_w32 = hot.words * 2;
+  uint32_t vis[K], nx[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const uint32_t w = (uint32_t)u[j] >> 6;
-    vis[j] = !ok[j] ? ~0ull : (w < hot.words ? hot.lds[w] : v.visited[w]);
+    const uint32_t w = (uint32_t)u[j] >> 5;
+    vis[j] = !ok[j] ? ~0u : (w < hot_w32 ? hot32[w] : vis32[w]);
   }
   bool need[K];
 #pragma unroll
-  for (int j = 0; j < K; ++j) need[j] = !((vis[j] >> (u[j] & 63)) & 1ull);
+  for (int j = 0; j < K; ++j) need[j] = !((vis[j] >> (u[j] & 31)) & 1u);
 #pragma unroll
-  for (int j = 0; j < K; ++j) nx[j] = need[j] ? v.next[(uint32_t)u[j] >> 6] : ~0ull;
+  for (int j = 0; j < K; ++j) nx[j] = need[j] ? next32[(uint32_t)u[j] >> 5] : ~0u;
 #pragma unroll
   for (int j = 0; j < K; ++j)
-    if (!((nx[j] >> (u[j] & 63)) & 1ull)) atomic_or_noret(v.next + ((uint32_t)u[j] >> 6), 1ull << (u[j] & 63));
+    if (!((nx[j] >> (u[j] & 31)) & 1u)) atomic_or_noret32(next32 + ((uint32_t)u[j] >> 5), 1u << (u[j] & 31));
 }
 
 // Per-lane totals of a queue-only level, reduced once per workgroup.
@@ -221,6 +230,7 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
   const uint64_t gwave = (uint64_t)vb_id * kWaves + wave;
   const uint64_t nwaves = (uint64_t)nvb * kWaves;
   SparseAcc acc;
+  uint64_t scanned = 0;  // wave-uniform: edges this wavefront scanned
 
   if (vb_id == 0 && threadIdx.x == 0) {
     const int r2 = (level + 2) % kRing;
@@ -243,6 +253,7 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     const int64_t b = v.rp[li], e = v.rp[li + 1];
     const int64_t lo = b + ((int64_t)(c - v.cstart[cur][s]) << v.chunk_shift);
     const int64_t hi = min(e, lo + (1ll << v.chunk_shift));
+    scanned += (uint64_t)(hi - lo);
     for (int64_t e0 = lo; e0 < hi; e0 += kWave * kUnroll) {
       int32_t u[kUnroll];
       bool ok[kUnroll];
@@ -261,6 +272,7 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
   for (uint64_t i = gwave; i < n1; i += nwaves) {
     const int64_t li = v.q1[cur][i] - v.vb;
     const int64_t b = v.rp[li], e = v.rp[li + 1];
+    scanned += (uint64_t)(e - b);
     for (int64_t k0 = b; k0 < e; k0 += kWave * kUnroll) {
       int32_t u[kUnroll];
       bool ok[kUnroll];
@@ -292,6 +304,7 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     // edge e of the batch is edge (e - excl[k]) of lane k's vertex, k the first
     // lane with incl[k] > e: its column index is col[start[k] - excl[k] + e]
     const int64_t rebase = start - (int64_t)(incl - deg);
+    scanned += (uint64_t)total;
     for (int32_t e0 = 0; e0 < total; e0 += kWave * kUnrollSmall) {
       int32_t u[kUnrollSmall];
       bool ok[kUnrollSmall];
@@ -311,6 +324,18 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     }
   }
 
+  if (!SPARSE) {
+    // Work done by the dense expansion (for the bandwidth accounting): edges
+    // scanned, one atomic per workgroup, and the frontier size.
+    if (lane == 0) s_acc[0][wave] = scanned;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t t = 0;
+      for (int w = 0; w < kWaves; ++w) t += s_acc[0][w];
+      if (t) atomic_add64(&v.ctl->xedges, t);
+      if (vb_id == 0) atomic_add64(&v.ctl->xfront, (uint64_t)n0 + n1 + n2);
+    }
+  }
   if (SPARSE) {
     // Level totals of the queue-only path: one atomic each per workgroup.
     const uint64_t a = (uint64_t)wave_sum((int64_t)acc.nnew);
@@ -578,11 +603,15 @@ __device__ __forceinline__ HotCache load_hot(const View &v, uint64_t *lds, uint3
 
 // hot_words > 0: the block keeps the first hot_words visited words in LDS
 // (the launch must provide hot_words * 8 bytes of dynamic LDS).
+// Queue-only level of the host-driven loop (its own kernel, so the dense
+// expansion keeps a small register budget).
+__global__ void __launch_bounds__(kBlock) k_expand_q(View v, int level) {
+  expand_phase<true>(v, v.dist, level, blockIdx.x, gridDim.x);
+}
+
 __global__ void __launch_bounds__(kBlock) k_expand(View v, int level, uint32_t hot_words) {
   extern __shared__ uint64_t s_hot[];
-  if (hot_words == kQueueOnly)
-    expand_phase<true>(v, v.dist, level, blockIdx.x, gridDim.x);
-  else if (hot_words)
+  if (hot_words)
     expand_phase<false>(v, v.dist, level, blockIdx.x, gridDim.x, load_hot(v, s_hot, hot_words));
   else
     expand_phase<false>(v, v.dist, level, blockIdx.x, gridDim.x);
@@ -802,7 +831,7 @@ hipError_t launch_reset(const View &v, int64_t src, int grid, hipStream_t s) {
 // hot_words == kQueueOnly runs a queue-only level (no LDS copy).
 hipError_t launch_expand(const View &v, int level, int grid, uint32_t hot_words, hipStream_t s) {
   if (hot_words == kQueueOnly)
-    hipLaunchKernelGGL(k_expand, dim3(grid), dim3(kBlock), 0, s, v, level, hot_words);
+    hipLaunchKernelGGL(k_expand_q, dim3(grid), dim3(kBlock), 0, s, v, level);
   else if (hot_words > kNarrowHotMax)
     hipLaunchKernelGGL(k_expand_wide, dim3(grid), dim3(kWideBlock), hot_words * 8, s, v, level, hot_words);
   else

@@ -90,6 +90,9 @@ __device__ __forceinline__ uint32_t wave_upper_slot(const uint32_t *a, uint32_t 
 __device__ __forceinline__ void atomic_or_noret(uint64_t *p, uint64_t v) {
   (void)__hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void atomic_or_noret32(uint32_t *p, uint32_t v) {
+  (void)__hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ uint64_t atomic_or64(uint64_t *p, uint64_t v) {
   return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -91,8 +91,9 @@ struct bfs_plan_s {
   int64_t last_level_new = 0;
   float last_ms = 0.f;
   float last_loop_ms = 0.f;
-  float last_expand_ms = 0.f, last_merge_ms = 0.f;
+  float last_expand_ms = 0.f, last_merge_ms = 0.f, last_queue_ms = 0.f;
   int32_t last_expand_launches = 0;
+  bool level_queue_only[kTimedLevels] = {};  // host-driven loop: level L ran queue-only
   std::vector<int64_t> level_frontier;
 
   // captured level-step graphs, one per graph index, with the settings they

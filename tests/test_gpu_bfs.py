@@ -57,6 +57,10 @@ MODES = [dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST),
          dict(loop_mode=pkg.LOOP_GRAPH, hot_words=16384),
          # one workgroup with the bitmaps in LDS (small whole graphs)
          dict(loop_mode=pkg.LOOP_CU), dict(loop_mode=pkg.LOOP_CU, relabel=-1),
+         # every level dense (bitmap merge), and queue-only levels up to a
+         # frontier of half the bitmap words
+         dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1), dict(loop_mode=pkg.LOOP_HOST, sparse_div=2),
+         dict(loop_mode=pkg.LOOP_PERSISTENT, sparse_div=-1),
          dict(loop_mode=pkg.LOOP_GRAPH, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64)]
 
 
@@ -122,7 +126,7 @@ def test_level_stats(gpu):
     s = int(gg.pick_sources(g, 1, seed=5)[0])
     ref = oracle.bfs(g, s)
     deg = g.degrees()
-    for mode in (pkg.LOOP_PERSISTENT, pkg.LOOP_HOST, pkg.LOOP_GRAPH):
+    for mode in (pkg.LOOP_PERSISTENT, pkg.LOOP_HOST, pkg.LOOP_GRAPH, pkg.LOOP_CU):
         dg = pkg.DeviceGraph.from_csr(g, gpu)
         plan = pkg.Plan([dg], loop_mode=mode, collect_stats=True)
         plan.run(0, s)
@@ -134,6 +138,29 @@ def test_level_stats(gpu):
             bins = np.where(deg[lv] > 0, np.floor(np.log2(np.maximum(deg[lv], 1))).astype(int) + 1, 0)
             assert np.array_equal(hist[L], np.bincount(bins, minlength=pkg.NUM_BINS)), L
         plan.close()
+
+
+def test_dense_work_accounting(gpu):
+    """The device's count of the work behind the dense expansions (the bytes
+    the benchmark's roofline figure divides by their time): with every level
+    dense it is the oracle's edges scanned and reached count; with queue-only
+    levels it is the sum over the levels whose frontier reached the threshold."""
+    g = gg.rmat(14, 8, seed=11, perm_seed=12)
+    s = int(gg.pick_sources(g, 1, seed=13)[0])
+    ref = oracle.bfs(g, s)
+    deg = g.degrees()
+    for mode in (pkg.LOOP_HOST, pkg.LOOP_PERSISTENT):
+        _, _, st = _run(g, s, gpu, loop_mode=mode, sparse_div=-1, autotune=-1)
+        assert st.dense_edges == oracle.edges_scanned(g, ref)
+        assert st.dense_frontier == int((ref >= 0).sum())
+    _, _, st = _run(g, s, gpu, loop_mode=pkg.LOOP_HOST, sparse_div=2, autotune=-1)
+    words = (g.n + 63) // 64
+    dense = [L for L in range(int(ref.max()) + 1) if int((ref == L).sum()) * 2 >= words]
+    assert 0 < len(dense) < int(ref.max()) + 1
+    assert st.expand_launches == len(dense)
+    assert st.dense_frontier == sum(int((ref == L).sum()) for L in dense)
+    assert st.dense_edges == sum(int(deg[ref == L].sum()) for L in dense)
+    assert st.queue_ms > 0 and st.expand_ms > 0
 
 
 # ---------------------------------------------------------------------------
