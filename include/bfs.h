@@ -114,7 +114,22 @@ typedef struct {
                               -1 = none */
   int32_t sparse_div;      /* single node: a level runs queue-only (no bitmap merge) when its
                               frontier is below ceil(n/64) / sparse_div; 0 = tuned, -1 = never */
+  int32_t direction;       /* BFS_DIR_TOPDOWN (default): every level top-down, the paper's
+                              method. BFS_DIR_OPTIMIZING: bfs_run on a whole graph without an
+                              exchange callback may run large levels bottom-up (see below);
+                              ignored otherwise. Distances are the same either way */
+  int32_t reserved;
 } bfs_options;
+
+#define BFS_DIR_TOPDOWN 0
+/* Direction-optimizing traversal (the bottom-up step the paper names as a
+   promising addition, Section 2 on direction-optimizing BFS; the switching
+   rule is the usual edge-count test). In the host-driven loop a level L >= 2
+   runs bottom-up -- every unvisited vertex scans its adjacency for a member of
+   the level-L frontier bitmap and stops at the first -- once the frontier's
+   edges exceed 1/14 of the unvisited vertices' edges, and returns to top-down
+   when the frontier shrinks below n/24 vertices. */
+#define BFS_DIR_OPTIMIZING 1
 
 /* Fills *o with defaults (all zero / NULL, loop_mode AUTO). */
 void bfs_options_default(bfs_options *o);
@@ -136,6 +151,10 @@ typedef struct {
   int64_t dense_frontier;  /* frontier vertices of those expansions */
   float queue_ms;          /* host-driven loop: device time of the queue-only levels (their
                               expansions are not in expand_ms) */
+  int32_t bottom_up_levels; /* levels that ran bottom-up (BFS_DIR_OPTIMIZING) */
+  float bottom_up_ms;      /* device time of their bottom-up launches (not in expand_ms) */
+  int64_t bottom_up_edges; /* adjacency entries the bottom-up launches examined */
+  int64_t bottom_up_vertices; /* unvisited vertices they examined */
 } bfs_stats;
 
 #define BFS_MAX_LEVEL_STATS 4096
@@ -177,6 +196,7 @@ typedef struct {
   int32_t hot_words;        /* visited words each expansion block keeps in LDS (0: none) */
   int32_t sparse_div;       /* single node: a level runs queue-only when its frontier is below
                                ceil(n/64) / sparse_div (0: never) */
+  int32_t direction;        /* BFS_DIR_* the traversal of this graph uses */
 } bfs_tuning;
 
 /* Fills *out (host) with the settings of graph `graph`. */

@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_WORKSPACE", 3: "ERR_HIP", 4: "ERR
                 5: "ERR_CAPACITY", 6: "ERR_EXCHANGE", 7: "ERR_STATE", 8: "ERR_TIMEOUT",
                 9: "ERR_DEVICE"}
 LOOP_AUTO, LOOP_HOST, LOOP_PERSISTENT, LOOP_GRAPH, LOOP_CU = 0, 1, 2, 3, 4
+DIR_TOPDOWN, DIR_OPTIMIZING = 0, 1
 OUT_U8, OUT_I32 = 0, 1
 BATCH_ONE_LAUNCH, BATCH_STREAMING = 1, 2
 NUM_BINS = 34
@@ -44,7 +45,8 @@ class bfs_options(ctypes.Structure):
                 ("batch_lanes", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
                 ("exchange", EXCHANGE_FN), ("exchange_ctx", ctypes.c_void_p),
                 ("relabel", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("hot_words", ctypes.c_int32), ("sparse_div", ctypes.c_int32)]
+                ("hot_words", ctypes.c_int32), ("sparse_div", ctypes.c_int32),
+                ("direction", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class bfs_stats(ctypes.Structure):
@@ -53,7 +55,9 @@ class bfs_stats(ctypes.Structure):
                 ("loop_ms", ctypes.c_float), ("expand_ms", ctypes.c_float),
                 ("merge_ms", ctypes.c_float), ("expand_launches", ctypes.c_int32),
                 ("dense_edges", ctypes.c_int64), ("dense_frontier", ctypes.c_int64),
-                ("queue_ms", ctypes.c_float)]
+                ("queue_ms", ctypes.c_float), ("bottom_up_levels", ctypes.c_int32),
+                ("bottom_up_ms", ctypes.c_float), ("bottom_up_edges", ctypes.c_int64),
+                ("bottom_up_vertices", ctypes.c_int64)]
 
 
 class bfs_tuning(ctypes.Structure):
@@ -61,7 +65,8 @@ class bfs_tuning(ctypes.Structure):
                 ("grid_blocks", ctypes.c_int32), ("small_bin", ctypes.c_int32),
                 ("wave_bin", ctypes.c_int32), ("chunk_edges", ctypes.c_int32),
                 ("relabelled", ctypes.c_int32), ("tuned_ms", ctypes.c_float),
-                ("hot_words", ctypes.c_int32), ("sparse_div", ctypes.c_int32)]
+                ("hot_words", ctypes.c_int32), ("sparse_div", ctypes.c_int32),
+                ("direction", ctypes.c_int32)]
 
 
 class bfs_query(ctypes.Structure):
@@ -181,7 +186,7 @@ class Plan:
 
     def __init__(self, graphs, *, loop_mode=LOOP_AUTO, small_bin=0, wave_bin=0, chunk_edges=0,
                  grid_blocks=0, batch_lanes=0, collect_stats=False, exchange=None, stream=None,
-                 relabel=0, autotune=0, hot_words=0, sparse_div=0):
+                 relabel=0, autotune=0, hot_words=0, sparse_div=0, direction=0):
         torch = _torch()
         L = lib()
         if isinstance(graphs, DeviceGraph):
@@ -199,6 +204,7 @@ class Plan:
         o.autotune = int(autotune)
         o.hot_words = int(hot_words)
         o.sparse_div = int(sparse_div)
+        o.direction = int(direction)
         self._exchange_py = exchange
         self._exchange_keep = None
         if exchange is not None:

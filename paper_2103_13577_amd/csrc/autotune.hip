@@ -132,6 +132,12 @@ bfs_status autotune_graphs(Plan *p) {
       c.loop_mode = BFS_LOOP_CU;
       loops.push_back(c);
     }
+    if (p->direction_optimizing((int32_t)gi)) {  // bfs_run then always drives the levels itself
+      loops.clear();
+      Tuning h = t;
+      h.loop_mode = BFS_LOOP_HOST;
+      loops.push_back(h);
+    }
     if (loops.empty()) loops.push_back(t);
     for (const Tuning &c : loops)
       if ((s = trial(c))) return s;

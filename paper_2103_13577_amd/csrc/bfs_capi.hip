@@ -51,6 +51,7 @@ void layout_single(const bfs_graph *g, int32_t ng, WsLayout &L, size_t &off) {
   L.lvl_hist = off; off = align_up(off + sizeof(uint32_t) * kMaxStatLevels * kNumBins, 256);
   L.visited = off; off = align_up(off + sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), 256);
   L.next = off; off = align_up(off + sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), 256);
+  L.front = off; off = align_up(off + sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), 256);
   for (int t = 0; t < 3; ++t)
     for (int p = 0; p < kRing; ++p) { L.q[t][p] = off; off = align_up(off + sizeof(int32_t) * (size_t)omax, 256); }
   for (int p = 0; p < kRing; ++p) { L.cstart[p] = off; off = align_up(off + sizeof(uint32_t) * (size_t)omax, 256); }
@@ -81,6 +82,7 @@ View bfs_plan_s::view(int32_t gi, int32_t *dist) const {
   v.dist = dist;
   v.visited = (uint64_t *)(b + lay.visited);
   v.next = (uint64_t *)(b + lay.next);
+  v.front = cur_do ? (uint64_t *)(b + lay.front) : nullptr;
   for (int p = 0; p < kRing; ++p) {
     v.q0[p] = (int32_t *)(b + lay.q[0][p]);
     v.q1[p] = (int32_t *)(b + lay.q[1][p]);
@@ -197,7 +199,13 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
   p->bpc[1] = persistent_blocks_per_cu(1);
   p->bpc_expand = expand_blocks_per_cu(0u);
   p->max_lds = (int)prop.sharedMemPerBlock;
+  p->bpc_bu = bottom_up_blocks_per_cu(kBottomUpHot);
   p->persist_grid = o->grid_blocks;  // 0: chosen per graph
+  if (o->direction != BFS_DIR_TOPDOWN && o->direction != BFS_DIR_OPTIMIZING) {
+    g_create_error = "unknown direction";
+    delete p;
+    return BFS_ERR_ARG;
+  }
   if (o->loop_mode < BFS_LOOP_AUTO || o->loop_mode > BFS_LOOP_CU) {
     g_create_error = "unknown loop_mode";
     delete p;
@@ -271,6 +279,11 @@ bfs_status begin_impl(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist
   p->cur_source = source;
   p->cur_dist = dist;
   p->cur_relabel = relabel;
+  p->cur_do = relabel && p->direction_optimizing(graph);
+  p->bu_state = false;
+  p->front_level = -1;
+  p->edges_after.clear();
+  p->bu_levels_run = 0;
   p->level = 0;
   p->expanded_level = -1;
   p->big_level = false;
@@ -302,7 +315,7 @@ bfs_status bfs_expand(bfs_plan_t p, const uint64_t **local_next) {
   if (p->expanded_level == p->level) return p->fail(BFS_ERR_STATE, "level already expanded");
   const bool timed = p->time_levels && p->level < Plan::kTimedLevels;
   if (timed) {
-    p->level_queue_only[p->level] = false;
+    p->level_kind[p->level] = 0;
     (void)hipEventRecord(p->lev[p->level][0], p->stream);
   }
   // The LDS copy of the hub bits pays off only on large dense levels.
@@ -350,6 +363,8 @@ bfs_status bfs_merge_frontier(bfs_plan_t p, const uint64_t *const *incoming, int
       if ((int)p->level_frontier.size() == p->level + 1)
         p->level_frontier.push_back((int64_t)c.ownedcnt[p->level % 3]);
       p->last_level_new = (int64_t)c.newcnt[p->level % 3];
+      p->edges_after.push_back((int64_t)c.edges);
+      if (v.front) p->front_level = p->level + 1;  // the merge wrote the next frontier bitmap
       p->level += 1;
     }
   }
@@ -369,7 +384,7 @@ bfs_status queue_only_level(bfs_plan_t p, int64_t *global_new) {
   }
   const bool timed = p->time_levels && p->level < Plan::kTimedLevels;
   if (timed) {
-    p->level_queue_only[p->level] = true;
+    p->level_kind[p->level] = 1;
     (void)hipEventRecord(p->lev[p->level][0], p->stream);
   }
   hipError_t e = launch_expand(v, p->level, p->wide_grid(), kQueueOnly, p->stream);
@@ -383,12 +398,39 @@ bfs_status queue_only_level(bfs_plan_t p, int64_t *global_new) {
   bfs_status st = p->read_ctl(c);
   if (st) return st;
   *global_new = (int64_t)c.newcnt[p->level % 3];
+  p->edges_after.push_back((int64_t)c.edges);
   p->big_level = (int64_t)c.ownedcnt[p->level % 3] * 16 >= v.n;
   if ((int)p->level_frontier.size() == p->level + 1)
     p->level_frontier.push_back((int64_t)c.ownedcnt[p->level % 3]);
   p->last_level_new = *global_new;
   p->level += 1;
   return BFS_OK;
+}
+
+// One bottom-up level of a direction-optimizing traversal: the frontier
+// bitmap (written by the previous merge, else rebuilt from the queues), the
+// bottom-up step into `next`, then the ordinary merge.
+bfs_status bottom_up_level(bfs_plan_t p, int64_t *global_new) {
+  View v = p->view(p->cur_graph, p->cur_dist);
+  if (p->opt.collect_stats && p->level + 1 < kMaxStatLevels) {
+    hipError_t e = launch_clear_stats_row(v, p->level + 1, p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "stats launch");
+  }
+  const bool timed = p->time_levels && p->level < Plan::kTimedLevels;
+  if (timed) {
+    p->level_kind[p->level] = 2;
+    (void)hipEventRecord(p->lev[p->level][0], p->stream);
+  }
+  hipError_t e = hipSuccess;
+  if (p->front_level != p->level) e = launch_front_from_queues(v, p->level, p->wide_grid(), p->stream);
+  const uint32_t hot = (uint32_t)std::min<int64_t>(kBottomUpHot, v.words);
+  if (e == hipSuccess)
+    e = launch_bottom_up(v, p->level, p->num_cus * std::max(p->bpc_bu, 1), hot, p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "bottom-up launch");
+  if (timed) (void)hipEventRecord(p->lev[p->level][1], p->stream);
+  p->expanded_level = p->level;
+  p->bu_levels_run += 1;
+  return bfs_merge_frontier(p, nullptr, 0, 0, global_new, nullptr);
 }
 
 }  // namespace
@@ -417,6 +459,10 @@ bfs_status bfs_finish(bfs_plan_t p, int32_t *parent, bfs_stats *st) {
     st->dense_edges = (int64_t)c.xedges;
     st->dense_frontier = (int64_t)c.xfront;
     st->queue_ms = p->last_queue_ms;
+    st->bottom_up_levels = p->bu_levels_run;
+    st->bottom_up_ms = p->last_bu_ms;
+    st->bottom_up_edges = (int64_t)c.buedges;
+    st->bottom_up_vertices = (int64_t)c.buverts;
   }
   return BFS_OK;
 }
@@ -475,7 +521,7 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   p->persistent_levels = 0;
   p->last_ms = 0.f;
   p->last_loop_ms = 0.f;
-  p->last_expand_ms = p->last_merge_ms = p->last_queue_ms = 0.f;
+  p->last_expand_ms = p->last_merge_ms = p->last_queue_ms = p->last_bu_ms = 0.f;
   p->last_expand_launches = 0;
   e = hipEventRecord(ev0, p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
@@ -484,7 +530,7 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   const bfs_graph &g = p->graphs[graph];
   const Tuning &tu = p->tune[graph];
   int mode = p->opt.loop_mode == BFS_LOOP_AUTO ? tu.loop_mode : p->opt.loop_mode;
-  if (p->opt.exchange) mode = BFS_LOOP_HOST;
+  if (p->opt.exchange || p->cur_do) mode = BFS_LOOP_HOST;  // the direction test runs on the host
   int grid = 0;
   if (mode == BFS_LOOP_PERSISTENT) {
     grid = p->persist_grid > 0 ? p->persist_grid : tu.persist_grid;
@@ -562,6 +608,25 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
     p->time_levels = true;
     const int64_t words = (g.n_global + 63) / 64;
     for (;;) {
+      if (p->cur_do && p->level >= 2) {
+        // edge-count test: frontier edges against the unvisited vertices' edges
+        const int L = p->level;
+        const int64_t mf = p->edges_after[L - 1] - p->edges_after[L - 2];
+        const int64_t mu = g.m - p->edges_after[L - 1];
+        const int64_t nf = p->level_frontier[L], nf_prev = p->level_frontier[L - 1];
+        if (!p->bu_state) {
+          if (mf * kDirAlpha > mu) p->bu_state = true;
+        } else if (nf * kDirBeta < g.n_global && nf < nf_prev) {
+          p->bu_state = false;
+        }
+        if (p->bu_state) {
+          int64_t gnew = 0;
+          s = bottom_up_level(p, &gnew);
+          if (s) { p->time_levels = false; return s; }
+          if (gnew == 0) break;
+          continue;
+        }
+      }
       // small frontiers of a single node run queue-only
       const int64_t fr = p->level_frontier.empty() ? 0 : p->level_frontier.back();
       if (!p->opt.exchange && tu.sparse_div > 0 && fr * tu.sparse_div < words) {
@@ -605,15 +670,20 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   if (hipEventElapsedTime(&lms, p->ev[2], ev1) != hipSuccess) lms = -1.f;
   p->last_ms = ms;
   p->last_loop_ms = lms;
-  p->last_expand_ms = p->last_merge_ms = p->last_queue_ms = 0.f;
+  p->last_expand_ms = p->last_merge_ms = p->last_queue_ms = p->last_bu_ms = 0.f;
   p->last_expand_launches = 0;
   if (host_loop) {
     const int nl = std::min(p->level, Plan::kTimedLevels);
     for (int L = 0; L < nl; ++L) {
       float a = 0.f, b = 0.f;
       if (hipEventElapsedTime(&a, p->lev[L][0], p->lev[L][1]) != hipSuccess) a = 0.f;
-      if (p->level_queue_only[L]) {
+      if (p->level_kind[L] == 1) {
         p->last_queue_ms += a;
+        continue;
+      }
+      if (p->level_kind[L] == 2) {
+        p->last_bu_ms += a;
+        if (hipEventElapsedTime(&b, p->lev[L][1], p->lev[L][2]) == hipSuccess) p->last_merge_ms += b;
         continue;
       }
       p->last_expand_ms += a;
@@ -639,6 +709,7 @@ bfs_status bfs_plan_tuning(bfs_plan_t p, int32_t graph, bfs_tuning *out) {
   out->tuned_ms = t.tuned_ms;
   out->hot_words = t.hot_words;
   out->sparse_div = t.sparse_div;
+  out->direction = p->direction_optimizing(graph) ? BFS_DIR_OPTIMIZING : BFS_DIR_TOPDOWN;
   return BFS_OK;
 }
 

@@ -15,6 +15,9 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kWideBlock = 1024;      // threads per workgroup of the wide expansion
 constexpr uint32_t kNarrowHotMax = 4096;  // larger LDS hub copies use the wide expansion
 constexpr uint32_t kQueueOnly = 0xFFFFFFFFu;  // k_expand: run a queue-only level
+constexpr uint32_t kBottomUpHot = 2048;       // frontier words a bottom-up block keeps in LDS
+constexpr int64_t kDirAlpha = 14;  // top-down -> bottom-up when frontier edges * 14 > unvisited edges
+constexpr int64_t kDirBeta = 24;   // bottom-up -> top-down when frontier * 24 < n and shrinking
 constexpr int kMaxStatLevels = 4096;
 constexpr int kHeavyShift = 40;  // packed heavy-tier counter: count << 40 | chunks
 constexpr uint64_t kChunkMask = (1ull << kHeavyShift) - 1;
@@ -37,6 +40,8 @@ struct Ctl {
   int32_t *gdist;         // graph-launched loop: caller's distance array
   uint64_t xedges;        // edges scanned by dense (bitmap) expansions
   uint64_t xfront;        // frontier vertices of dense expansions
+  uint64_t buedges;       // adjacency entries examined by bottom-up steps
+  uint64_t buverts;       // unvisited vertices examined by bottom-up steps
 };
 
 // Kernel view of a plan's workspace for one graph.
@@ -52,6 +57,8 @@ struct View {
   int32_t *dist;          // indexed by caller ids
   uint64_t *visited;
   uint64_t *next;
+  uint64_t *front;        // direction-optimizing traversal: frontier bitmap of the
+                          // next level, written by every dense merge (NULL: off)
   int32_t *q0[kRing];
   int32_t *q1[kRing];
   int32_t *q2[kRing];
@@ -103,6 +110,9 @@ hipError_t enqueue_graph_levels(const View &v, int levels, int max_levels, int e
                                 int merge_grid, uint32_t hot_words, hipStream_t s);
 int persistent_blocks_per_cu(int variant);
 int expand_blocks_per_cu(uint32_t hot_words);
+hipError_t launch_bottom_up(const View &v, int level, int grid, uint32_t hot_words, hipStream_t s);
+hipError_t launch_front_from_queues(const View &v, int level, int grid, hipStream_t s);
+int bottom_up_blocks_per_cu(uint32_t hot_words);
 size_t cu_lds_bytes(int64_t words);
 bool cu_fits(int64_t n, int64_t m, bool whole, int max_lds);
 hipError_t launch_bfs_cu(const View &v, int64_t src, int max_levels, hipStream_t s);

@@ -60,6 +60,8 @@ __global__ void __launch_bounds__(kBlock) k_reset(View v, int64_t src_caller) {
     c->gdist = v.dist;
     c->xedges = 0;
     c->xfront = 0;
+    c->buedges = 0;
+    c->buverts = 0;
     const bool owned = src >= v.vb && src < v.ve;
     int64_t deg = 0;
     if (owned) {
@@ -418,6 +420,7 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
         v.next[w] = 0ull;
       }
       if (w == v.words - 1 && (v.n & 63)) nw &= ~0ull >> (64 - (v.n & 63));
+      if (v.front && !a.keep_next) v.front[w] = nw;  // the next level's frontier bitmap
       om = nw & owned_mask(w, v.vb, v.ve);
     }
     my_new += (uint64_t)__popcll(nw);
@@ -629,6 +632,113 @@ __global__ void __launch_bounds__(kWideBlock) k_expand_wide(View v, int level, u
 
 __global__ void __launch_bounds__(kBlock) k_merge(View v, MergeArgs a) {
   merge_phase(v, v.dist, a, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// bottom-up step (direction-optimizing traversal, single node, whole graph)
+// ---------------------------------------------------------------------------
+
+constexpr int kBuUnroll = 4;  // adjacency entries per lane in flight
+
+// Level L bottom-up: one wavefront per 64-vertex word of `visited`, one lane
+// per unvisited vertex. A lane scans its vertex's adjacency kBuUnroll entries
+// at a time until a neighbour is set in the level-L frontier bitmap; the
+// vertices found in a word go to `next` with one store (each word belongs to
+// one wavefront), and the ordinary merge then finishes the level (distances,
+// visited, queues and the next frontier bitmap). The first frontier words are
+// copied to LDS: on a relabelled graph every adjacency list starts with the
+// hubs, so the first probes of most lanes are LDS reads.
+__global__ void __launch_bounds__(kBlock) k_bottom_up(View v, int level, uint32_t hot_words) {
+  extern __shared__ uint64_t s_hot[];
+  __shared__ uint64_t s_acc[2][kWavesPerBlock];
+  const int lane = lane_id();
+  const uint32_t wave = threadIdx.x / kWave;
+  const uint64_t gwave = (uint64_t)blockIdx.x * kWavesPerBlock + wave;
+  const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // the ring bookkeeping of an expansion
+    const int r2 = (level + 2) % kRing;
+    v.ctl->qn[r2][0] = 0;
+    v.ctl->qn[r2][1] = 0;
+    v.ctl->heavy[r2] = 0;
+    v.ctl->newcnt[(level + 1) % 3] = 0;
+    v.ctl->ownedcnt[(level + 1) % 3] = 0;
+  }
+  const uint32_t hw = (uint32_t)min<int64_t>(hot_words, v.words);
+  for (uint32_t i = threadIdx.x; i < hw; i += kBlock) s_hot[i] = v.front[i];
+  __syncthreads();
+  uint64_t examined = 0, verts = 0;
+  for (uint64_t w = gwave; w < (uint64_t)v.words; w += nwaves) {
+    const uint64_t vis = v.visited[w];
+    if (vis == ~0ull) continue;
+    const int64_t x = (int64_t)w * 64 + lane;
+    bool todo = x < v.n && !((vis >> lane) & 1ull);
+    int64_t k = 0, e = 0;
+    if (todo) {
+      k = v.rp[x];
+      e = v.rp[x + 1];
+      todo = k < e;
+    }
+    const int64_t k0 = k;
+    bool found = false;
+    while (ballot(todo && !found && k < e)) {
+      if (todo && !found && k < e) {
+        int32_t u[kBuUnroll];
+#pragma unroll
+        for (int j = 0; j < kBuUnroll; ++j) u[j] = (k + j < e) ? v.col[k + j] : -1;
+#pragma unroll
+        for (int j = 0; j < kBuUnroll; ++j) {
+          if (u[j] >= 0) {
+            const uint32_t uw = (uint32_t)u[j] >> 6;
+            const uint64_t fw = uw < hw ? s_hot[uw] : v.front[uw];
+            if ((fw >> (u[j] & 63)) & 1ull) found = true;
+          }
+        }
+        k += kBuUnroll;
+      }
+    }
+    if (todo) {
+      examined += (uint64_t)(min(k, e) - k0);
+      verts += 1;
+    }
+    const uint64_t fm = ballot(found);
+    if (lane == 0 && fm) v.next[w] = fm;
+  }
+  const uint64_t te = (uint64_t)wave_sum((int64_t)examined);
+  const uint64_t tv = (uint64_t)wave_sum((int64_t)verts);
+  if (lane == 0) {
+    s_acc[0][wave] = te;
+    s_acc[1][wave] = tv;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t a = 0, b = 0;
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+      a += s_acc[0][i];
+      b += s_acc[1][i];
+    }
+    if (a) atomic_add64(&v.ctl->buedges, a);
+    if (b) atomic_add64(&v.ctl->buverts, b);
+  }
+}
+
+// Frontier bitmap of level L from its tier queues (after a queue-only level,
+// which leaves the frontier in queues only): clear, then set every entry.
+__global__ void __launch_bounds__(kBlock) k_front_zero(View v) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t w = tid; w < v.words; w += (int64_t)gridDim.x * blockDim.x) v.front[w] = 0ull;
+}
+
+__global__ void __launch_bounds__(kBlock) k_front_scatter(View v, int level) {
+  const int cur = level % kRing;
+  const uint64_t n0 = load_relaxed32(&v.ctl->qn[cur][0]);
+  const uint64_t n1 = load_relaxed32(&v.ctl->qn[cur][1]);
+  const uint64_t n2 = load_relaxed64(&v.ctl->heavy[cur]) >> kHeavyShift;
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = tid; i < n0 + n1 + n2; i += stride) {
+    const int32_t x = i < n0 ? v.q0[cur][i] : (i < n0 + n1 ? v.q1[cur][i - n0] : v.q2[cur][i - n0 - n1]);
+    atomic_or_noret(v.front + (x >> 6), 1ull << (x & 63));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -852,6 +962,27 @@ hipError_t launch_clear_stats_row(const View &v, int level, hipStream_t s) {
 hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_parent, dim3(grid), dim3(kBlock), 0, s, v, parent, src);
   return hipGetLastError();
+}
+
+hipError_t launch_bottom_up(const View &v, int level, int grid, uint32_t hot_words, hipStream_t s) {
+  hipLaunchKernelGGL(k_bottom_up, dim3(grid), dim3(kBlock), (size_t)hot_words * 8, s, v, level, hot_words);
+  return hipGetLastError();
+}
+
+hipError_t launch_front_from_queues(const View &v, int level, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_front_zero, dim3(grid), dim3(kBlock), 0, s, v);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_front_scatter, dim3(grid), dim3(kBlock), 0, s, v, level);
+  return hipGetLastError();
+}
+
+int bottom_up_blocks_per_cu(uint32_t hot_words) {
+  int nb = 0;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_bottom_up, kBlock, (size_t)hot_words * 8) ==
+                 hipSuccess
+             ? nb
+             : 0;
 }
 
 // Co-resident blocks per CU of the per-phase expansion kernel that an LDS

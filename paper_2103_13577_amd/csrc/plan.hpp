@@ -21,7 +21,7 @@ namespace bfsk {
 
 // Byte offsets of the workspace regions.
 struct WsLayout {
-  size_t ctl, lvl_frontier, lvl_hist, visited, next;
+  size_t ctl, lvl_frontier, lvl_hist, visited, next, front;
   size_t q[3][kRing];
   size_t cstart[kRing];
   // batched multi-source state (see msbfs_core.hpp)
@@ -93,7 +93,20 @@ struct bfs_plan_s {
   float last_loop_ms = 0.f;
   float last_expand_ms = 0.f, last_merge_ms = 0.f, last_queue_ms = 0.f;
   int32_t last_expand_launches = 0;
-  bool level_queue_only[kTimedLevels] = {};  // host-driven loop: level L ran queue-only
+  // host-driven loop: how level L ran (0 dense top-down, 1 queue-only, 2 bottom-up)
+  uint8_t level_kind[kTimedLevels] = {};
+  float last_bu_ms = 0.f;
+  int32_t bu_levels_run = 0;
+  // direction-optimizing traversal (bfs_run, whole graph, no exchange)
+  bool cur_do = false;                // the running traversal may go bottom-up
+  bool bu_state = false;              // the current level runs bottom-up
+  int front_level = -1;               // level whose frontier the front bitmap holds
+  std::vector<int64_t> edges_after;   // edge counter (sum of reached degrees) after each level
+  int bpc_bu = 0;                     // co-resident bottom-up blocks per CU
+  bool direction_optimizing(int32_t gi) const {
+    return opt.direction == BFS_DIR_OPTIMIZING && !opt.exchange && graphs[gi].v_begin == 0 &&
+           graphs[gi].v_end == graphs[gi].n_global;
+  }
   std::vector<int64_t> level_frontier;
 
   // captured level-step graphs, one per graph index, with the settings they

@@ -61,6 +61,9 @@ MODES = [dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST),
          # frontier of half the bitmap words
          dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1), dict(loop_mode=pkg.LOOP_HOST, sparse_div=2),
          dict(loop_mode=pkg.LOOP_PERSISTENT, sparse_div=-1),
+         # direction-optimizing: large levels bottom-up (next row of the paper's outlook)
+         dict(direction=pkg.DIR_OPTIMIZING),
+         dict(direction=pkg.DIR_OPTIMIZING, sparse_div=-1, relabel=-1),
          dict(loop_mode=pkg.LOOP_GRAPH, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64)]
 
 
@@ -137,6 +140,34 @@ def test_level_stats(gpu):
             assert front[L] == lv.size
             bins = np.where(deg[lv] > 0, np.floor(np.log2(np.maximum(deg[lv], 1))).astype(int) + 1, 0)
             assert np.array_equal(hist[L], np.bincount(bins, minlength=pkg.NUM_BINS)), L
+        plan.close()
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(sparse_div=-1), dict(relabel=-1, autotune=-1)])
+def test_direction_optimizing_exact(gpu, opts):
+    """Bottom-up levels give the oracle's distances and canonical parents, and
+    on R-MAT they run on the large levels. Covers the frontier bitmap written by a
+    merge (sparse_div=-1: every level dense) and rebuilt from the queues after
+    a queue-only level."""
+    import torch
+    for scale, nsrc in ((14, 24), (17, 6)):
+        g = gg.rmat(scale, 16, seed=60 + scale, perm_seed=70 + scale)
+        dg = pkg.DeviceGraph.from_csr(g, gpu)
+        plan = pkg.Plan([dg], direction=pkg.DIR_OPTIMIZING, **opts)
+        assert plan.tuning(0)["direction"] == pkg.DIR_OPTIMIZING
+        bu_runs = 0
+        for s in gg.pick_sources(g, nsrc, seed=80 + scale):
+            print(f"[gpu] DO rmat{scale} src={s} {opts}", flush=True)
+            d, p, st = plan.run(0, int(s), parent=True)
+            ref = oracle.bfs(g, int(s))
+            assert np.array_equal(d.cpu().numpy(), ref)
+            assert np.array_equal(p.cpu().numpy(), oracle.parent(g, ref))
+            assert st.edges_scanned == oracle.edges_scanned(g, ref)
+            assert st.levels == int(ref.max()) + 1
+            if st.bottom_up_levels:
+                bu_runs += 1
+                assert st.bottom_up_edges > 0 and st.bottom_up_vertices > 0
+        assert bu_runs >= nsrc // 2, bu_runs
         plan.close()
 
 
