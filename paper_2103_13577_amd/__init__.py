@@ -168,6 +168,7 @@ class DeviceGraph:
 
 @dataclass
 class Stats:
+    """One traversal's counters and device times (the fields of ``bfs_stats``)."""
     levels: int
     reached: int
     edges_scanned: int
@@ -176,6 +177,17 @@ class Stats:
     expand_ms: float = 0.0
     merge_ms: float = 0.0
     expand_launches: int = 0
+    dense_edges: int = 0
+    dense_frontier: int = 0
+    queue_ms: float = 0.0
+    bottom_up_levels: int = 0
+    bottom_up_ms: float = 0.0
+    bottom_up_edges: int = 0
+    bottom_up_vertices: int = 0
+
+    @classmethod
+    def from_c(cls, st: "bfs_stats") -> "Stats":
+        return cls(**{f: getattr(st, f) for f, _ in bfs_stats._fields_})
 
 
 class Plan:
@@ -270,7 +282,7 @@ class Plan:
         st = bfs_stats()
         self._check(lib().bfs_run(self.h, graph, int(source), dist.data_ptr(),
                                   par.data_ptr() if par is not None else None, ctypes.byref(st)))
-        return dist, par, Stats(st.levels, st.reached, st.edges_scanned, st.ms, st.loop_ms, st.expand_ms, st.merge_ms, st.expand_launches)
+        return dist, par, Stats.from_c(st)
 
     def begin(self, graph: int, source: int, dist):
         self._check(lib().bfs_begin(self.h, graph, int(source), dist.data_ptr()))
@@ -296,7 +308,7 @@ class Plan:
         st = bfs_stats()
         self._check(lib().bfs_finish(self.h, parent.data_ptr() if parent is not None else None,
                                      ctypes.byref(st)))
-        return Stats(st.levels, st.reached, st.edges_scanned, st.ms, st.loop_ms, st.expand_ms, st.merge_ms, st.expand_launches)
+        return Stats.from_c(st)
 
     def tuning(self, graph: int = 0) -> dict:
         """Settings the plan uses for one graph (after autotuning)."""

@@ -47,3 +47,9 @@ def test_create_error_without_device():
     assert b"bad sizes" in L.bfs_last_error(None)
     sz = ctypes.c_size_t(0)
     assert L.bfs_workspace_size(None, 0, None, ctypes.byref(sz)) == 1
+
+
+def test_stats_wrapper_mirrors_c_struct():
+    """The Python Stats record carries every field of bfs_stats."""
+    import paper_2103_13577_amd as pkg
+    assert [f for f, _ in pkg.bfs_stats._fields_] == list(pkg.Stats.__dataclass_fields__)
