@@ -110,19 +110,24 @@ struct HotCache {
   const uint64_t *lds;
   uint32_t words;
 };
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
 template <int K>
 __device__ __forceinline__ void probe_batch(const View &v, const int32_t (&u)[K],
                                             const bool (&ok)[K], HotCache hot) {
   const uint32_t *vis32 = reinterpret_cast<const uint32_t *>(v.visited);
   uint32_t *next32 = reinterpret_cast<uint32_t *>(v.next);
-  const uint32_t *hot32 = reinterpret_cast<const uint32_t *>(hot.lds);
+  // the copy is read through an LDS-qualified pointer so the reads are LDS
+  // instructions rather than generic (flat) loads
+  const lds_u32 *hot32 = (const lds_u32 *)(hot.lds);
   const uint32_t hot_w32 = hot.words * 2;
   uint32_t vis[K], nx[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const uint32_t w = (uint32_t)u[j] >> 5;
-    vis[j] = !ok[j] ? ~0u : (w < hot_w32 ? hot32[w] : vis32[w]);
+    if (!ok[j]) vis[j] = ~0u;
+    else if (w < hot_w32) vis[j] = hot32[w];
+    else vis[j] = vis32[w];
   }
   bool need[K];
 #pragma unroll
@@ -689,7 +694,10 @@ __global__ void __launch_bounds__(kBlock) k_bottom_up(View v, int level, uint32_
         for (int j = 0; j < kBuUnroll; ++j) {
           if (u[j] >= 0) {
             const uint32_t uw = (uint32_t)u[j] >> 6;
-            const uint64_t fw = uw < hw ? s_hot[uw] : v.front[uw];
+            // address-space-qualified reads stay LDS and global instructions
+            uint64_t fw;
+            if (uw < hw) fw = s_hot[uw];
+            else fw = ((const __attribute__((address_space(1))) uint64_t *)v.front)[uw];
             if ((fw >> (u[j] & 63)) & 1ull) found = true;
           }
         }

@@ -219,11 +219,12 @@ __device__ __forceinline__ bool ms_update_vertex(const MsView &v, int L, bool va
         const int slot = (g * LW + l) * 64 + b;
         const int32_t val = L + 1 - v.slot_start[slot];
         const uint64_t ptr = v.slot_out[slot];
+        // outputs are device memory: global stores, not generic (flat) ones
         if (v.slot_type[slot] == 0) {
           if (val > 254) atomic_or64(&v.depth_err[g * LW + l], 1ull << b);
-          else ((uint8_t *)ptr)[xl] = (uint8_t)val;
+          else ((__attribute__((address_space(1))) uint8_t *)ptr)[xl] = (uint8_t)val;
         } else {
-          ((int32_t *)ptr)[xl] = val;
+          ((__attribute__((address_space(1))) int32_t *)ptr)[xl] = val;
         }
       }
     }
