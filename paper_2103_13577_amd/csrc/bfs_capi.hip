@@ -358,8 +358,9 @@ bfs_status bfs_merge_frontier(bfs_plan_t p, const uint64_t *const *incoming, int
     if (global_new) *global_new = (int64_t)c.newcnt[p->level % 3];
     if (owned_new) *owned_new = (int64_t)c.ownedcnt[p->level % 3];
     if (!keep_next) {
-      // the next level is "big" when its frontier is a sizable share of the graph
-      p->big_level = (int64_t)c.ownedcnt[p->level % 3] * 16 >= v.n;
+      // the next level is "big" (worth an LDS copy of the hub bits) when its
+      // frontier's edges are at least the vertex count
+      p->big_level = (int64_t)c.edges - (p->edges_after.empty() ? 0 : p->edges_after.back()) >= v.n;
       if ((int)p->level_frontier.size() == p->level + 1)
         p->level_frontier.push_back((int64_t)c.ownedcnt[p->level % 3]);
       p->last_level_new = (int64_t)c.newcnt[p->level % 3];
@@ -398,8 +399,8 @@ bfs_status queue_only_level(bfs_plan_t p, int64_t *global_new) {
   bfs_status st = p->read_ctl(c);
   if (st) return st;
   *global_new = (int64_t)c.newcnt[p->level % 3];
+  p->big_level = (int64_t)c.edges - (p->edges_after.empty() ? 0 : p->edges_after.back()) >= v.n;
   p->edges_after.push_back((int64_t)c.edges);
-  p->big_level = (int64_t)c.ownedcnt[p->level % 3] * 16 >= v.n;
   if ((int)p->level_frontier.size() == p->level + 1)
     p->level_frontier.push_back((int64_t)c.ownedcnt[p->level % 3]);
   p->last_level_new = *global_new;

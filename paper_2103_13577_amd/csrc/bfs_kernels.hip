@@ -121,14 +121,23 @@ __device__ __forceinline__ void probe_batch(const View &v, const int32_t (&u)[K]
   // instructions rather than generic (flat) loads
   const lds_u32 *hot32 = (const lds_u32 *)(hot.lds);
   const uint32_t hot_w32 = hot.words * 2;
-  uint32_t vis[K], nx[K];
+  // LDS and global reads land in separate registers: when both wrote one
+  // register the compiler had to wait for each global read before issuing
+  // the next LDS read, which serialised the K probes.
+  uint32_t w[K], lv[K], gv[K], vis[K], nx[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) w[j] = (uint32_t)u[j] >> 5;  // u is 0 where !ok
+  if (hot_w32) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) lv[j] = hot32[min(w[j], hot_w32 - 1)];
+  }
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const uint32_t w = (uint32_t)u[j] >> 5;
-    if (!ok[j]) vis[j] = ~0u;
-    else if (w < hot_w32) vis[j] = hot32[w];
-    else vis[j] = vis32[w];
+    gv[j] = ~0u;
+    if (ok[j] && w[j] >= hot_w32) gv[j] = vis32[w[j]];
   }
+#pragma unroll
+  for (int j = 0; j < K; ++j) vis[j] = !ok[j] ? ~0u : (w[j] < hot_w32 ? lv[j] : gv[j]);
   bool need[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) need[j] = !((vis[j] >> (u[j] & 31)) & 1u);
