@@ -317,8 +317,12 @@ def run_serve(args):
         gs.append(g)
         log(f"generated {name}: n={g.n} m={g.m} ({time.time() - t0:.0f}s)")
     dgs = [pkg.DeviceGraph.from_csr(g, dev) for g in gs]
-    plan = pkg.Plan(dgs, batch_lanes=args.serve_lanes, grid_blocks=args.grid_blocks)
+    # the serving plan's own single-source settings are not used by the
+    # batched path, so it skips the autotuner; the plain baseline is tuned
+    log("planning (the baseline plan autotunes each graph)")
+    plan = pkg.Plan(dgs, batch_lanes=args.serve_lanes, grid_blocks=args.grid_blocks, autotune=-1)
     single = pkg.Plan(dgs, grid_blocks=args.grid_blocks)
+    log("plans ready")
     arrivals = gg.poisson_arrivals(nq, 20000.0, seed=0x5EED0550)
     gsel = (gg.draws(0x5EED0551, nq) % np.uint64(len(gs))).astype(np.int64)
     srcs = np.zeros(nq, dtype=np.int64)
@@ -370,7 +374,10 @@ def run_serve(args):
                 with cv:
                     free[gi].append(bi)
                     state["completed"] += 1
+                    ncomp = state["completed"]
                     cv.notify_all()
+                if ncomp % 500 == 0:
+                    log(f"served {ncomp}/{nq}")
 
     th = threading.Thread(target=consumer, daemon=True)
     th.start()
@@ -405,7 +412,10 @@ def run_serve(args):
     torch.cuda.synchronize()
     t = time.perf_counter()
     svc = []
-    for q in samp:
+    log(f"plain one-at-a-time sample of {samp.size} queries")
+    for k, q in enumerate(samp):
+        if k % 20 == 0:
+            log(f"plain {k}/{samp.size}")
         gi = int(gsel[q])
         ts = time.perf_counter()
         d, _, _ = single.run(gi, int(srcs[q]), dist=pools[gi][0])
