@@ -124,7 +124,8 @@ def run_single(args, name, scale, ef):
     dg = pkg.DeviceGraph.from_csr(g, dev)
     plan = pkg.Plan([dg], loop_mode=args.loop_mode, grid_blocks=args.grid_blocks,
                     small_bin=args.small_bin, wave_bin=args.wave_bin, chunk_edges=args.chunk_edges,
-                    relabel=args.relabel, autotune=args.autotune, hot_words=args.hot_words)
+                    relabel=args.relabel, autotune=args.autotune, hot_words=args.hot_words,
+                    sparse_div=args.sparse_div, direction=args.direction)
     srcs = gg.pick_sources(g, args.warmup + args.steps, seed=sseed)
     dist = torch.empty(g.n, dtype=torch.int32, device=dev)
     for s in srcs[:args.warmup]:
@@ -144,7 +145,21 @@ def run_single(args, name, scale, ef):
     rates = edges / (ms * 1e-3) / 1e9
     hmean = metrics.harmonic_mean(rates)
     tuning = plan.tuning(0)
-    if tuning["loop_mode"] == 1:
+    if tuning["direction"] == 1:
+        # direction-optimizing: the dominant kernel is the bottom-up step.
+        # Per launch it reads two int64 row offsets per unvisited vertex it
+        # examines (16 B) and the column index of every adjacency entry it
+        # loads (4 B); the device counts both, and the launches are timed with
+        # HIP events on the plan's stream.
+        kname = "k_bottom_up"
+        bu_ms = np.array([s.bottom_up_ms for s in stats])
+        launches = np.array([s.bottom_up_levels for s in stats])
+        k_bytes = np.array([4.0 * s.bottom_up_edges + 16.0 * s.bottom_up_vertices for s in stats])
+        achieved = float(np.sum(k_bytes) / max(np.sum(bu_ms) * 1e-3, 1e-12) / 1e9)
+        per_launch_bytes = float(np.sum(k_bytes) / max(np.sum(launches), 1))
+        avg_launch_ms = float(np.sum(bu_ms) / max(np.sum(launches), 1))
+        n_launches = int(np.sum(launches))
+    elif tuning["loop_mode"] == 1:
         # host-driven loop: the dominant kernel is the dense expansion
         # (k_expand). Per launch it reads the column index of every edge it
         # scans (4 B) and two int64 row offsets per frontier vertex (16 B);
@@ -186,7 +201,8 @@ def run_single(args, name, scale, ef):
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"single-source top-down BFS, R-MAT scale {scale} edge factor {ef} "
+        "config": {"workload": f"single-source {'direction-optimizing' if args.direction else 'top-down'} "
+                               f"BFS, R-MAT scale {scale} edge factor {ef} "
                                f"(A=.57,B=.19,C=.19), symmetrised, int32 CSR, "
                                f"{args.steps} seeded sources one at a time",
                    "n": g.n, "m_directed": g.m, "sources": args.steps,
@@ -709,6 +725,9 @@ def main():
     ap.add_argument("--relabel", type=int, default=0, help="0 auto, 1 on, -1 off")
     ap.add_argument("--autotune", type=int, default=0, help="0 auto, 1 on, -1 off")
     ap.add_argument("--hot-words", type=int, default=0, help="0 tuned, -1 none")
+    ap.add_argument("--sparse-div", type=int, default=0, help="0 tuned, -1 never queue-only")
+    ap.add_argument("--direction", type=int, default=0,
+                    help="0 top-down (the paper's method), 1 direction-optimizing")
     ap.add_argument("--no-cpu-baseline", dest="cpu_baseline", action="store_false")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=int, default=0)
