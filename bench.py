@@ -166,7 +166,7 @@ def run_single(args, name, scale, ef):
         # the device counts both, and each launch is timed with HIP events on
         # the plan's stream. Queue-only levels (small frontiers) run another
         # kernel and are not part of this figure.
-        kname = "k_expand"
+        kname = "k_expand+k_expand_wide" if tuning["hot_words"] > 4096 else "k_expand"
         exp_ms = np.array([s.expand_ms for s in stats])
         launches = np.array([s.expand_launches for s in stats])
         k_bytes = np.array([4.0 * s.dense_edges + 16.0 * s.dense_frontier for s in stats])
@@ -186,7 +186,7 @@ def run_single(args, name, scale, ef):
         per_launch_bytes = float(np.mean(k_bytes))
         avg_launch_ms = float(np.mean(loop_ms))
         n_launches = len(stats)
-    traffic = measured_traffic(kname, per_launch_bytes)
+    traffic = measured_traffic(_dense_series(kname), per_launch_bytes)
     whole_bytes = np.array([metrics.bytes_single_source(e, r, g.n) for e, r in zip(edges, reached)])
     out = {
         "metric": "GTEPS (1 MI355X, all edges) + batched queries/sec with p50/p99 latency",
@@ -598,7 +598,22 @@ def _bench_line(log_path):
 
 
 def _short(name):
-    return name.split("(")[0].split("::")[-1].strip('"')
+    """Kernel name without namespaces, template arguments and parameters."""
+    import re
+    n = name.strip('"').replace("(anonymous namespace)", "")
+    while True:  # drop innermost template argument lists
+        m = re.sub(r"<[^<>]*>", "", n)
+        if m == n:
+            break
+        n = m
+    n = n.split("(")[0].strip()
+    return n.split("::")[-1].split()[-1] if n else name
+
+
+def _dense_series(kname):
+    """The dense expansion runs as k_expand, or as k_expand_wide on levels with
+    a large LDS hub copy: profiles treat both as one series."""
+    return "k_expand+k_expand_wide" if kname.split("+")[0] == "k_expand" else kname
 
 
 def summarize_pmc(args):
@@ -614,17 +629,23 @@ def summarize_pmc(args):
     line = _bench_line(fetch_log)
     timed = line["roofline"].get("launches", 0)
 
+    group = _dense_series(line["roofline"]["kernel"])
+    members = set(group.split("+"))
+
     def per_kernel(d, counter, last=0):
         vals = defaultdict(lambda: defaultdict(float))
         with open(os.path.join(d, "run_counter_collection.csv")) as f:
             for r in csv.DictReader(f):
                 if r["Counter_Name"] != counter:
                     continue
-                vals[_short(r["Kernel_Name"])][int(r["Dispatch_Id"])] += float(r["Counter_Value"])
+                k = _short(r["Kernel_Name"])
+                if k in members:
+                    k = group  # the roofline's kernel (or kernels) as one series
+                vals[k][int(r["Dispatch_Id"])] += float(r["Counter_Value"])
         out, cnt = {}, {}
         for k, per in vals.items():
             ids = sorted(per)
-            if last and k in ("k_expand", "k_merge"):
+            if last and k in (group, "k_merge"):
                 ids = ids[-last:]
             out[k] = sum(per[i] for i in ids) / len(ids)
             cnt[k] = len(ids)
@@ -639,12 +660,13 @@ def summarize_pmc(args):
     fscale, wscale = copy_kib / cf[ck], copy_kib / cw[ck]
     out = {"workload": "R-MAT scale 24 edge factor 16, host-driven level loop",
            "plan": line["config"].get("plan"),
+           "commands": args.pmc_commands,
            "kernel_source_hash": kernel_source_hash(),
            "copy_probe": {"bytes": args.copy_bytes, "fetch_kib": cf[ck], "write_kib": cw[ck],
                           "fetch_scale": fscale, "write_scale": wscale},
            "kernels": {}}
     for k in fetch:
-        if k not in ("k_expand", "k_merge", "k_reset"):
+        if k not in (group, "k_merge", "k_reset"):
             continue
         fb = fetch[k] * fscale * 1024
         wb = write.get(k, 0.0) * wscale * 1024
@@ -670,12 +692,14 @@ def summarize_trace(args):
     roof = line["roofline"]
     kname, timed = roof["kernel"], roof.get("launches", 0)
     rows = list(csv.DictReader(open(os.path.join(d, "run_kernel_stats.csv"))))
-    durs = defaultdict(list)
+    kname = _dense_series(kname)
+    members = set(kname.split("+"))
+    sel = []
     with open(os.path.join(d, "run_kernel_trace.csv")) as f:
         for r in csv.DictReader(f):
-            durs[_short(r["Kernel_Name"])].append(
-                (int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
-    sel = sorted(durs.get(kname, []))
+            if _short(r["Kernel_Name"]) in members:
+                sel.append((int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    sel.sort()
     if timed:
         sel = sel[-timed:]
     avg_ms = sum(x for _, x in sel) / max(len(sel), 1) / 1e6
@@ -740,6 +764,8 @@ def main():
                                                          "COPY_WRITE_DIR", "FETCH_RUN_LOG"))
     ap.add_argument("--summarize-trace", nargs=4, metavar=("TRACE_DIR", "RUN_LOG", "OUT_NAME",
                                                            "COMMAND"))
+    ap.add_argument("--pmc-commands", nargs="*", default=[],
+                    help="the rocprofv3 commands the --summarize-pmc runs came from (recorded)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     args = ap.parse_args()
     if args.gpus != 1:

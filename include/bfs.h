@@ -185,7 +185,8 @@ const char *bfs_last_error(bfs_plan_t p);
 
 /* Settings the plan uses for one graph (after autotuning). */
 typedef struct {
-  int32_t loop_mode;        /* BFS_LOOP_HOST, BFS_LOOP_PERSISTENT or BFS_LOOP_GRAPH */
+  int32_t loop_mode;        /* the level loop bfs_run drives (BFS_LOOP_HOST, _PERSISTENT, _GRAPH
+                               or _CU): the option when given, else the tuned choice */
   int32_t persist_variant;  /* 0: default registers, 1: 64-VGPR budget */
   int32_t grid_blocks;      /* blocks of the persistent launch */
   int32_t small_bin;

@@ -700,7 +700,11 @@ bfs_status bfs_plan_tuning(bfs_plan_t p, int32_t graph, bfs_tuning *out) {
   if (graph < 0 || graph >= (int32_t)p->graphs.size() || !out)
     return p->fail(BFS_ERR_ARG, "bad graph index or NULL output");
   const Tuning &t = p->tune[graph];
-  out->loop_mode = t.loop_mode;
+  // the loop bfs_run drives: an explicit option wins over the tuned choice,
+  // and an exchange callback or a direction-optimizing traversal needs the
+  // host-driven loop
+  out->loop_mode = p->opt.loop_mode != BFS_LOOP_AUTO ? p->opt.loop_mode : t.loop_mode;
+  if (p->opt.exchange || p->direction_optimizing(graph)) out->loop_mode = BFS_LOOP_HOST;
   out->persist_variant = t.persist_variant;
   out->grid_blocks = p->persist_grid > 0 ? p->persist_grid : t.persist_grid;
   out->small_bin = t.small_bin;
