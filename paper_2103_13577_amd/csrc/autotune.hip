@@ -148,7 +148,7 @@ bfs_status autotune_graphs(Plan *p) {
     }
     // 2. tier thresholds (degree bins), each kept only if it helps
     if (p->opt.small_bin <= 0)
-      for (int sb : {5, 7, 8, 9, 10, 11}) {
+      for (int sb : {4, 5, 7, 8, 9, 10, 11}) {
         Tuning c = best;
         c.small_bin = sb;
         if (c.wave_bin < sb) continue;

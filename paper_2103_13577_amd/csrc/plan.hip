@@ -137,7 +137,8 @@ bfs_status choose_tuning(Plan *p) {
       while ((1 << s) < p->opt.chunk_edges && s < 30) ++s;
       t.chunk_shift = s;
     }
-    if (t.small_bin < 1 || t.small_bin > 24 || t.wave_bin < t.small_bin || t.chunk_shift < 6)
+    if (t.small_bin < 1 || t.small_bin > 24 || t.wave_bin < t.small_bin || t.wave_bin > 25 ||
+        t.chunk_shift < 6)
       return p->fail(BFS_ERR_ARG, "bad tier thresholds");
     // untuned default: the cooperative loop with the 64-VGPR budget, one
     // block per 16K edges and vertices of the share (a small grid keeps the
