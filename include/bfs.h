@@ -92,8 +92,8 @@ typedef struct {
   void *hip_stream;        /* hipStream_t; NULL = the null stream */
   int32_t loop_mode;       /* BFS_LOOP_* */
   int32_t small_bin;       /* degree bins b < small_bin -> lane-group tier (1..24); 0 = tuned */
-  int32_t wave_bin;        /* bins small_bin <= b < wave_bin (at most 25) -> batched wavefront
-                              tier, else the chunked hub tier; 0 = tuned */
+  int32_t wave_bin;        /* bins small_bin <= b < wave_bin (at most 25) -> wavefront tier,
+                              else the chunked hub tier; 0 = tuned */
   int32_t chunk_edges;     /* edges per block-tier work item (power of two); 0 = default */
   int32_t grid_blocks;     /* workgroups for device-resident loops; 0 = sized to the graph */
   int32_t batch_lanes;     /* 64-source lane words per graph for batched BFS; 0 = none */

@@ -283,45 +283,20 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     }
   }
 
-  // Tier 1: batches of 64 medium-degree vertices per wavefront. A batch's
-  // adjacency lists are read as one stream of 64-edge rows (consecutive queue
-  // entries have neighbouring rows, so the reads coalesce), and the row
-  // offsets of all 64 vertices are loaded at once. Every tier-1 degree is at
-  // least dmin = 2^(small_bin-1), so a row meets at most ceil(64/dmin) + 1
-  // vertices: a lane finds its vertex by comparing its edge index with the
-  // prefix sums of those few, read as scalars from a wave-uniform cursor.
+  // Tier 1: one wavefront per vertex.
   const uint32_t n1 = load_relaxed32(&v.ctl->qn[cur][1]);
-  const int span = (kWave >> min(v.small_bin - 1, 6)) + 2;  // candidate vertices per row
-  for (uint64_t base = gwave * kWave; base < n1; base += nwaves * kWave) {
-    const uint64_t i = base + lane;
-    int64_t start = 0;
-    int32_t deg = 0;  // below 2^24 (wave_bin <= 25): a batch's prefix sums fit in 32 bits
-    if (i < n1) {
-      const int64_t li = v.q1[cur][i] - v.vb;
-      start = v.rp[li];
-      deg = (int32_t)(v.rp[li + 1] - start);
-    }
-    const int32_t incl = wave_incl_scan32(deg);
-    const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
-    const int64_t rebase = start - (int64_t)(incl - deg);
-    scanned += (uint64_t)total;
-    int k = 0;  // wave-uniform: first lane whose prefix passes the current row start
-    for (int32_t e0 = 0; e0 < total; e0 += kWave * kUnroll) {
+  for (uint64_t i = gwave; i < n1; i += nwaves) {
+    const int64_t li = v.q1[cur][i] - v.vb;
+    const int64_t b = v.rp[li], e = v.rp[li + 1];
+    scanned += (uint64_t)(e - b);
+    for (int64_t k0 = b; k0 < e; k0 += kWave * kUnroll) {
       int32_t u[kUnroll];
       bool ok[kUnroll];
 #pragma unroll
       for (int j = 0; j < kUnroll; ++j) {
-        const int32_t rs = e0 + j * kWave;
-        while (k < kWave - 1 && __builtin_amdgcn_readlane(incl, k) <= rs) ++k;
-        const int32_t e = rs + lane;
-        int64_t rb = readlane64((uint64_t)rebase, k);
-        for (int c = 0; c + 1 < span && k + c + 1 < kWave; ++c) {
-          const int32_t ic = __builtin_amdgcn_readlane(incl, k + c);
-          const int64_t rn = (int64_t)readlane64((uint64_t)rebase, k + c + 1);
-          if (ic <= e) rb = rn;
-        }
-        ok[j] = e < total;
-        u[j] = ok[j] ? load_col(v.col, rb + e) : 0;
+        const int64_t k = k0 + (int64_t)j * kWave + lane;
+        ok[j] = k < e;
+        u[j] = ok[j] ? load_col(v.col, k) : 0;
       }
       probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc, hot, dist);
     }
