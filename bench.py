@@ -769,8 +769,9 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
-              f"multi-GPU path: the exchange between nodes is described, not built.",
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no "
+              f"multi-GPU path; the exchange between nodes goes through the caller's "
+              f"exchange callback or the step-wise calls, and none is driven here.",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
