@@ -104,15 +104,15 @@ bfs_status autotune_graphs(Plan *p) {
       loops.push_back(h);
     }
     if (p->coop && (p->opt.loop_mode == BFS_LOOP_AUTO || p->opt.loop_mode == BFS_LOOP_PERSISTENT)) {
-      // grids: all co-resident blocks, half of them, one block per CU and
-      // one per four CUs (fewer blocks make each grid barrier cheaper, which
-      // wins on small graphs)
+      // grids: all co-resident blocks, half of them, one block per CU, one
+      // per four CUs, 32 and 8 blocks (every block pays each grid barrier's
+      // release and acquire, so small graphs want few blocks)
       for (int var = 0; var < 2; ++var) {
         const int bpc = p->bpc[var];
         if (bpc <= 0) continue;
         const int cap = std::min(bpc * p->num_cus, kBarrierGroup * kBarrierMaxGroups);
         int last = -1;
-        for (int grid : {cap, (bpc / 2) * p->num_cus, p->num_cus, p->num_cus / 4}) {
+        for (int grid : {cap, (bpc / 2) * p->num_cus, p->num_cus, p->num_cus / 4, 32, 8}) {
           grid = std::min(grid, cap);
           if (p->persist_grid > 0) grid = p->persist_grid;
           if (grid <= 0 || grid == last) continue;

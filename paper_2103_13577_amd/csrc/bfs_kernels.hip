@@ -235,7 +235,7 @@ __device__ __forceinline__ void probe_dispatch(const View &v, const int32_t (&u)
 // first clears the counters of the ring slot two levels ahead (read at level
 // L-1, not written before level L+1). Every loop below runs the same number
 // of iterations on all lanes of a wavefront (queue-only levels use ballots).
-template <bool SPARSE, int BLOCK = kBlock>
+template <bool SPARSE, int BLOCK = kBlock, int KU = kUnroll, int KS = kUnrollSmall>
 __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int level, uint32_t vb_id,
                                              uint32_t nvb, HotCache hot = HotCache{nullptr, 0}) {
   constexpr int kWaves = BLOCK / kWave;
@@ -270,16 +270,16 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     const int64_t lo = b + ((int64_t)(c - v.cstart[cur][s]) << v.chunk_shift);
     const int64_t hi = min(e, lo + (1ll << v.chunk_shift));
     scanned += (uint64_t)(hi - lo);
-    for (int64_t e0 = lo; e0 < hi; e0 += kWave * kUnroll) {
-      int32_t u[kUnroll];
-      bool ok[kUnroll];
+    for (int64_t e0 = lo; e0 < hi; e0 += kWave * KU) {
+      int32_t u[KU];
+      bool ok[KU];
 #pragma unroll
-      for (int j = 0; j < kUnroll; ++j) {
+      for (int j = 0; j < KU; ++j) {
         const int64_t k = e0 + (int64_t)j * kWave + lane;
         ok[j] = k < hi;
         u[j] = ok[j] ? load_col(v.col, k) : 0;
       }
-      probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc, hot, dist);
+      probe_dispatch<SPARSE, KU>(v, u, ok, level, acc, hot, dist);
     }
   }
 
@@ -289,16 +289,16 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     const int64_t li = v.q1[cur][i] - v.vb;
     const int64_t b = v.rp[li], e = v.rp[li + 1];
     scanned += (uint64_t)(e - b);
-    for (int64_t k0 = b; k0 < e; k0 += kWave * kUnroll) {
-      int32_t u[kUnroll];
-      bool ok[kUnroll];
+    for (int64_t k0 = b; k0 < e; k0 += kWave * KU) {
+      int32_t u[KU];
+      bool ok[KU];
 #pragma unroll
-      for (int j = 0; j < kUnroll; ++j) {
+      for (int j = 0; j < KU; ++j) {
         const int64_t k = k0 + (int64_t)j * kWave + lane;
         ok[j] = k < e;
         u[j] = ok[j] ? load_col(v.col, k) : 0;
       }
-      probe_dispatch<SPARSE, kUnroll>(v, u, ok, level, acc, hot, dist);
+      probe_dispatch<SPARSE, KU>(v, u, ok, level, acc, hot, dist);
     }
   }
 
@@ -321,11 +321,11 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     // lane with incl[k] > e: its column index is col[start[k] - excl[k] + e]
     const int64_t rebase = start - (int64_t)(incl - deg);
     scanned += (uint64_t)total;
-    for (int32_t e0 = 0; e0 < total; e0 += kWave * kUnrollSmall) {
-      int32_t u[kUnrollSmall];
-      bool ok[kUnrollSmall];
+    for (int32_t e0 = 0; e0 < total; e0 += kWave * KS) {
+      int32_t u[KS];
+      bool ok[KS];
 #pragma unroll
-      for (int j = 0; j < kUnrollSmall; ++j) {
+      for (int j = 0; j < KS; ++j) {
         const int32_t e = e0 + j * kWave + lane;
         int k = 0;
 #pragma unroll
@@ -336,7 +336,7 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
         ok[j] = e < total;
         u[j] = ok[j] ? load_col(v.col, rk + e) : 0;
       }
-      probe_dispatch<SPARSE, kUnrollSmall>(v, u, ok, level, acc, hot, dist);
+      probe_dispatch<SPARSE, KS>(v, u, ok, level, acc, hot, dist);
     }
   }
 
@@ -638,10 +638,12 @@ __global__ void __launch_bounds__(kBlock) k_expand(View v, int level, uint32_t h
 // up to ~144 KB of hub bits (on a degree-relabelled R-MAT graph the first 16K
 // words hold the targets of most edges), instead of four 256-thread blocks
 // each holding a small copy.
+// One block per CU leaves each wavefront up to 128 VGPRs: it keeps twice the
+// edges per lane in flight.
 __global__ void __launch_bounds__(kWideBlock) k_expand_wide(View v, int level, uint32_t hot_words) {
   extern __shared__ uint64_t s_hot[];
-  expand_phase<false, kWideBlock>(v, v.dist, level, blockIdx.x, gridDim.x,
-                                  load_hot<kWideBlock>(v, s_hot, hot_words));
+  expand_phase<false, kWideBlock, 2 * kUnroll, 2 * kUnrollSmall>(
+      v, v.dist, level, blockIdx.x, gridDim.x, load_hot<kWideBlock>(v, s_hot, hot_words));
 }
 
 __global__ void __launch_bounds__(kBlock) k_merge(View v, MergeArgs a) {

@@ -142,15 +142,14 @@ bfs_status choose_tuning(Plan *p) {
       return p->fail(BFS_ERR_ARG, "bad tier thresholds");
     // untuned default: the cooperative loop with the 64-VGPR budget, one
     // block per 16K edges and vertices of the share (a small grid keeps the
-    // grid barriers of small graphs cheap), between a quarter of the CUs and
-    // 8 blocks per CU; else launches per phase
+    // grid barriers of small graphs cheap), between 16 blocks and 8 blocks
+    // per CU; else launches per phase
     const int64_t m = p->graphs[i].m;
     t.persist_variant = p->bpc[1] > 0 ? 1 : 0;
     const int per_cu = std::min(p->bpc[t.persist_variant], 8);
     const int64_t work_grid = (m + (p->graphs[i].v_end - p->graphs[i].v_begin) + (1 << 14) - 1) >> 14;
     const int64_t max_grid = std::min(per_cu * p->num_cus, kBarrierGroup * kBarrierMaxGroups);
-    t.persist_grid = (int)std::max<int64_t>(
-        1, std::min<int64_t>(max_grid, std::max<int64_t>(work_grid, p->num_cus / 4)));
+    t.persist_grid = (int)std::max<int64_t>(1, std::min<int64_t>(max_grid, std::max<int64_t>(work_grid, 16)));
     t.loop_mode = (p->coop && per_cu > 0) ? BFS_LOOP_PERSISTENT : BFS_LOOP_HOST;
     // small whole graphs: one workgroup with the bitmaps in LDS
     const bfs_graph &gr = p->graphs[i];
