@@ -148,6 +148,70 @@ __device__ __forceinline__ void probe_batch(const View &v, const int32_t (&u)[K]
     if (!((nx[j] >> (u[j] & 31)) & 1u)) atomic_or_noret32(next32 + ((uint32_t)u[j] >> 5), 1u << (u[j] & 31));
 }
 
+// Dense probes of one adjacency range [b, e) (e > b), K rows of 64 entries at
+// a time, software-pipelined: the visited reads of a row group are issued
+// before the column loads of the next group (scheduling barriers keep that
+// order), so waiting for the visited words does not wait for the next group's
+// columns, which stay in flight while this group's next-words and ORs are
+// done. Every load is issued unconditionally (lanes with nothing to read use
+// a clamped index or word 0): loads under per-lane branches made the compiler
+// wait for all outstanding loads.
+template <int K>
+__device__ __forceinline__ void dense_rows_pipelined(const View &v, int64_t b, int64_t e, HotCache hot) {
+  const int lane = lane_id();
+  const uint32_t *vis32 = reinterpret_cast<const uint32_t *>(v.visited);
+  uint32_t *next32 = reinterpret_cast<uint32_t *>(v.next);
+  const lds_u32 *hot32 = (const lds_u32 *)(hot.lds);
+  const uint32_t hot_w32 = hot.words * 2;
+  int32_t u[K];
+  bool ok[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int64_t k = b + (int64_t)j * kWave + lane;
+    ok[j] = k < e;
+    u[j] = load_col(v.col, min(k, e - 1));
+  }
+  for (int64_t k0 = b; k0 < e; k0 += kWave * K) {
+    uint32_t w[K], lv[K], gv[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) w[j] = (uint32_t)u[j] >> 5;
+    if (hot_w32) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) lv[j] = hot32[min(w[j], hot_w32 - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) gv[j] = vis32[(ok[j] && w[j] >= hot_w32) ? w[j] : 0u];
+    __builtin_amdgcn_sched_barrier(0);
+    int32_t un[K];
+    bool okn[K];
+    const int64_t k1 = k0 + kWave * K;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int64_t k = k1 + (int64_t)j * kWave + lane;
+      okn[j] = k < e;
+      un[j] = load_col(v.col, min(k, e - 1));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    bool need[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const uint32_t vis = w[j] < hot_w32 ? lv[j] : gv[j];
+      need[j] = ok[j] && !((vis >> (u[j] & 31)) & 1u);
+    }
+    uint32_t nx[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) nx[j] = next32[need[j] ? w[j] : 0u];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if (need[j] && !((nx[j] >> (u[j] & 31)) & 1u)) atomic_or_noret32(next32 + w[j], 1u << (u[j] & 31));
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      u[j] = un[j];
+      ok[j] = okn[j];
+    }
+  }
+}
+
 // Per-lane totals of a queue-only level, reduced once per workgroup.
 struct SparseAcc {
   uint64_t nnew = 0, owned = 0, edges = 0;
@@ -289,6 +353,10 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     const int64_t li = v.q1[cur][i] - v.vb;
     const int64_t b = v.rp[li], e = v.rp[li + 1];
     scanned += (uint64_t)(e - b);
+    if (!SPARSE) {
+      dense_rows_pipelined<KU>(v, b, e, hot);
+      continue;
+    }
     for (int64_t k0 = b; k0 < e; k0 += kWave * KU) {
       int32_t u[KU];
       bool ok[KU];
