@@ -148,67 +148,55 @@ __device__ __forceinline__ void probe_batch(const View &v, const int32_t (&u)[K]
     if (!((nx[j] >> (u[j] & 31)) & 1u)) atomic_or_noret32(next32 + ((uint32_t)u[j] >> 5), 1u << (u[j] & 31));
 }
 
-// Dense probes of one adjacency range [b, e) (e > b), K rows of 64 entries at
-// a time, software-pipelined: the visited reads of a row group are issued
-// before the column loads of the next group (scheduling barriers keep that
-// order), so waiting for the visited words does not wait for the next group's
-// columns, which stay in flight while this group's next-words and ORs are
-// done. Every load is issued unconditionally (lanes with nothing to read use
-// a clamped index or word 0): loads under per-lane branches made the compiler
-// wait for all outstanding loads.
+// Dense probes of one adjacency range of `deg` entries starting at `row`
+// (wave-uniform), K rows of 64 entries at a time. Addresses are a uniform
+// base plus 32-bit lane offsets, so a row costs few vector instructions: the
+// column load index is clamped (no per-lane branch around it), visited words
+// of hub targets come from the LDS copy and the rest from global memory into
+// separate registers, and only lanes whose target is unvisited read `next`
+// and OR into it.
 template <int K>
-__device__ __forceinline__ void dense_rows_pipelined(const View &v, int64_t b, int64_t e, HotCache hot) {
+__device__ __forceinline__ void dense_rows(const View &v, const int32_t *row, int32_t deg, HotCache hot) {
   const int lane = lane_id();
   const uint32_t *vis32 = reinterpret_cast<const uint32_t *>(v.visited);
   uint32_t *next32 = reinterpret_cast<uint32_t *>(v.next);
   const lds_u32 *hot32 = (const lds_u32 *)(hot.lds);
   const uint32_t hot_w32 = hot.words * 2;
-  int32_t u[K];
-  bool ok[K];
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    const int64_t k = b + (int64_t)j * kWave + lane;
-    ok[j] = k < e;
-    u[j] = load_col(v.col, min(k, e - 1));
-  }
-  for (int64_t k0 = b; k0 < e; k0 += kWave * K) {
-    uint32_t w[K], lv[K], gv[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) w[j] = (uint32_t)u[j] >> 5;
-    if (hot_w32) {
-#pragma unroll
-      for (int j = 0; j < K; ++j) lv[j] = hot32[min(w[j], hot_w32 - 1)];
-    }
-#pragma unroll
-    for (int j = 0; j < K; ++j) gv[j] = vis32[(ok[j] && w[j] >= hot_w32) ? w[j] : 0u];
-    __builtin_amdgcn_sched_barrier(0);
-    int32_t un[K];
-    bool okn[K];
-    const int64_t k1 = k0 + kWave * K;
+  for (int32_t r0 = 0; r0 < deg; r0 += kWave * K) {
+    int32_t u[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      const int64_t k = k1 + (int64_t)j * kWave + lane;
-      okn[j] = k < e;
-      un[j] = load_col(v.col, min(k, e - 1));
+      // 32-bit byte offset from a scalar base (deg < 2^30)
+      const uint32_t off = (uint32_t)min(r0 + j * kWave + lane, deg - 1) << 2;
+      u[j] = __builtin_nontemporal_load(
+          reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(row) + off));
     }
-    __builtin_amdgcn_sched_barrier(0);
+    uint32_t lv[K], gv[K];
+    if (hot_w32) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) lv[j] = hot32[min((uint32_t)u[j] >> 5, hot_w32 - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      gv[j] = 0u;
+      if (((uint32_t)u[j] >> 5) >= hot_w32) gv[j] = vis32[(uint32_t)u[j] >> 5];
+    }
     bool need[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      const uint32_t vis = w[j] < hot_w32 ? lv[j] : gv[j];
-      need[j] = ok[j] && !((vis >> (u[j] & 31)) & 1u);
+      const uint32_t w = (uint32_t)u[j] >> 5;
+      const uint32_t vis = w < hot_w32 ? lv[j] : gv[j];
+      need[j] = r0 + j * kWave + lane < deg && !((vis >> (u[j] & 31)) & 1u);
     }
     uint32_t nx[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) nx[j] = next32[need[j] ? w[j] : 0u];
+    for (int j = 0; j < K; ++j) {
+      nx[j] = ~0u;
+      if (need[j]) nx[j] = next32[(uint32_t)u[j] >> 5];
+    }
 #pragma unroll
     for (int j = 0; j < K; ++j)
-      if (need[j] && !((nx[j] >> (u[j] & 31)) & 1u)) atomic_or_noret32(next32 + w[j], 1u << (u[j] & 31));
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      u[j] = un[j];
-      ok[j] = okn[j];
-    }
+      if (!((nx[j] >> (u[j] & 31)) & 1u)) atomic_or_noret32(next32 + ((uint32_t)u[j] >> 5), 1u << (u[j] & 31));
   }
 }
 
@@ -334,6 +322,11 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     const int64_t lo = b + ((int64_t)(c - v.cstart[cur][s]) << v.chunk_shift);
     const int64_t hi = min(e, lo + (1ll << v.chunk_shift));
     scanned += (uint64_t)(hi - lo);
+    if (!SPARSE) {
+      const int64_t ulo = uniform64(lo);
+      dense_rows<KU>(v, v.col + ulo, (int32_t)(uniform64(hi) - ulo), hot);
+      continue;
+    }
     for (int64_t e0 = lo; e0 < hi; e0 += kWave * KU) {
       int32_t u[KU];
       bool ok[KU];
@@ -354,7 +347,8 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     const int64_t b = v.rp[li], e = v.rp[li + 1];
     scanned += (uint64_t)(e - b);
     if (!SPARSE) {
-      dense_rows_pipelined<KU>(v, b, e, hot);
+      const int64_t ub = uniform64(b);
+      dense_rows<KU>(v, v.col + ub, (int32_t)(uniform64(e) - ub), hot);
       continue;
     }
     for (int64_t k0 = b; k0 < e; k0 += kWave * KU) {

@@ -27,6 +27,14 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// A wave-uniform value held in vector registers, moved to scalar registers
+// (so address arithmetic on it is scalar).
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int64_t shfl64(int64_t x, int src) {
   int lo = __shfl((int)(uint32_t)(uint64_t)x, src);
   int hi = __shfl((int)(uint32_t)((uint64_t)x >> 32), src);
