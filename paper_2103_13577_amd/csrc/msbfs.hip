@@ -7,7 +7,10 @@
 // and carries its own start level), launches the cooperative level loop over
 // all graphs at once, retires slots whose traversal has ended and completes
 // tickets. Slot memory is the admission budget: with no free slot a query
-// waits until one is released.
+// waits until one is released. A streaming launch runs at most 256 levels and
+// ends early when a slot of a graph with waiting queries finishes, so long
+// traversals (high-diameter graphs) are not cut into many short launches by
+// queries of other graphs.
 
 #include <hip/hip_runtime.h>
 
@@ -169,7 +172,7 @@ bfs_status batch_init(Plan *p) {
   v.slot_out = (uint64_t *)(w + L.ms_slot_out);
   v.slot_type = (int32_t *)(w + L.ms_slot_type);
   v.slot_start = (int32_t *)(w + L.ms_slot_start);
-  v.slot_active = (uint64_t *)(w + L.ms_slot_active);
+  v.stop_slots = (uint64_t *)(w + L.ms_slot_active);
   v.newmask = (uint64_t *)(w + L.ms_newmask);
   v.depth_err = (uint64_t *)(w + L.ms_depth_err);
   const Tuning &t = p->tune.empty() ? Tuning{} : p->tune[0];
@@ -288,9 +291,12 @@ bool BatchState::step(std::unique_lock<std::mutex> &lk) {
       maxn = std::max(maxn, ghost[g].n);
     }
   }
+  // A streaming launch stops early only when a slot of a graph with waiting
+  // queries finishes (the freed slot can then be refilled); slots of other
+  // graphs finish silently and are retired when the launch ends.
   bool still_pending = false;
   for (int g = 0; g < ng; ++g) still_pending |= !pending[g].empty();
-  for (int i = 0; i < nslotw; ++i) h_mask[nslotw + i] = active[i];
+  for (int i = 0; i < nslotw; ++i) h_mask[nslotw + i] = pending[i / lw].empty() ? 0ull : active[i];
   const bool streaming = still_pending || streaming_mode;
   lk.unlock();
 
@@ -309,11 +315,13 @@ bool BatchState::step(std::unique_lock<std::mutex> &lk) {
   if (e == hipSuccess) e = ms_launch_fill(d_adm, nadm, maxn, stream);
   if (e == hipSuccess) e = ms_launch_admit(view, d_adm, nadm, level, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(view.slot_active, h_mask + nslotw, sizeof(uint64_t) * nslotw,
+    e = hipMemcpyAsync(view.stop_slots, h_mask + nslotw, sizeof(uint64_t) * nslotw,
                        hipMemcpyHostToDevice, stream);
   MsView v = view;
   v.stream_stop = streaming ? 1 : 0;
-  const int max_levels = streaming ? (still_pending ? 8 : 64) : (1 << 20);
+  // Streaming launches also end after kStreamLevels levels, which bounds how
+  // long a newly submitted query waits for admission.
+  const int max_levels = streaming ? kStreamLevels : (1 << 20);
   if (e == hipSuccess) e = ms_launch_persistent(v, max_levels, grid, stream);
   MsCtl ctl{};
   if (e == hipSuccess) e = hipMemcpyAsync(&ctl, view.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, stream);

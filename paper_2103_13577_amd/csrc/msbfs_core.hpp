@@ -19,6 +19,7 @@ namespace bfsk {
 constexpr int kMsMaxGraphs = 16;
 constexpr int kMsMaxLW = 4;
 constexpr int kMsChunk = 256;  // vertices per sweep work item (one workgroup)
+constexpr int kStreamLevels = 256;  // most levels of one streaming launch
 
 struct MsGraph {
   int64_t off;          // first flat vertex
@@ -59,11 +60,11 @@ struct MsView {
   uint64_t *slot_out;        // [ng*lw*64] device pointers of the outputs
   int32_t *slot_type;        // 0 = uint8, 1 = int32
   int32_t *slot_start;       // level at which the slot's source is expanded
-  uint64_t *slot_active;     // [ng*lw] occupied slots
+  uint64_t *stop_slots;      // [ng*lw] occupied slots whose finish ends a streaming launch
   uint64_t *newmask;         // [3][ng*lw] slots with a new vertex in level L
   uint64_t *depth_err;       // [ng*lw] uint8 slots whose depth exceeded 254
   int32_t small_bin, wave_bin, chunk_shift;
-  int32_t stream_stop;       // stop a launch at the first level a slot finishes
+  int32_t stream_stop;       // stop a launch at the first level a slot of stop_slots finishes
   int32_t sparse_shift;      // a graph runs sparse when active * 2^shift < n
 };
 

@@ -423,7 +423,7 @@ __global__ void __launch_bounds__(kBlock) k_ms_persistent(MsView v, int max_leve
     if (!stop && v.stream_stop) {
       const int nslotw = v.ng * LW;
       for (int i = 0; i < nslotw; ++i)
-        if (v.slot_active[i] & ~load_relaxed64(&v.newmask[(L % 3) * nslotw + i])) {
+        if (v.stop_slots[i] & ~load_relaxed64(&v.newmask[(L % 3) * nslotw + i])) {
           stop = true;
           early = true;
           break;
