@@ -346,11 +346,13 @@ def run_serve(args):
         idx = np.flatnonzero(gsel == gi)
         srcs[idx] = gg.pick_sources(gs[gi], idx.size, seed=0x5EED0560 + gi)
     # output buffers: a pool per graph bounds the memory held by queries in
-    # flight or waiting; a query takes a buffer at its arrival (waiting for one
-    # if none is free: that wait counts in its latency)
+    # flight; a query takes a buffer at its arrival, or waits in its graph's
+    # queue until one of that graph's buffers is released (that wait counts in
+    # its latency; queries of other graphs are not held up)
     per_graph = args.serve_buffers
     pools = [[torch.empty(g.n, dtype=torch.int32, device=dev) for _ in range(per_graph)] for g in gs]
     free = [list(range(per_graph)) for _ in gs]
+    waitq = [[] for _ in gs]
     cv = threading.Condition()
     hash_w = {g.n: None for g in gs}
     for n in hash_w:
@@ -365,13 +367,19 @@ def run_serve(args):
     hashes = [None] * nq
     done_t = np.zeros(nq)
     tk_info = {}        # ticket -> (query, graph, buffer)
-    state = {"submitted": 0, "completed": 0, "done_submitting": False}
+    state = {"completed": 0}
     errors = []
+
+    def submit(q, gi, bi):
+        """Submits query q into buffer bi of its graph (called with cv held)."""
+        tk = plan.batch_submit([(gi, int(srcs[q]), pools[gi][bi])], pkg.BATCH_STREAMING)
+        tk_info[tk] = (q, gi, bi)
+        cv.notify_all()
 
     def consumer():
         while True:
             with cv:
-                if state["done_submitting"] and state["completed"] == state["submitted"]:
+                if state["completed"] == nq:
                     return
             for tk in plan.batch_poll(1024, timeout_us=2000):
                 try:
@@ -388,9 +396,12 @@ def run_serve(args):
                     done_t[q] = r.complete_ns * 1e-9
                     hashes[q] = out_hash(pools[gi][bi])
                 with cv:
-                    free[gi].append(bi)
                     state["completed"] += 1
                     ncomp = state["completed"]
+                    if waitq[gi]:
+                        submit(waitq[gi].pop(0), gi, bi)  # the released buffer goes to the next waiting query
+                    else:
+                        free[gi].append(bi)
                     cv.notify_all()
                 if ncomp % 500 == 0:
                     log(f"served {ncomp}/{nq}")
@@ -406,16 +417,10 @@ def run_serve(args):
             time.sleep(delay)
         gi = int(gsel[q])
         with cv:
-            while not free[gi]:
-                cv.wait()
-            bi = free[gi].pop()
-            state["submitted"] += 1
-        tk = plan.batch_submit([(gi, int(srcs[q]), pools[gi][bi])], pkg.BATCH_STREAMING)
-        with cv:
-            tk_info[tk] = (q, gi, bi)
-            cv.notify_all()
-    with cv:
-        state["done_submitting"] = True
+            if free[gi]:
+                submit(q, gi, free[gi].pop())
+            else:
+                waitq[gi].append(q)
     th.join()
     t_end = max(done_t)
     arr_abs = t_start_mono + arrivals  # steady-clock time of each arrival
