@@ -250,6 +250,8 @@ def run_batch(args):
     dgs = [pkg.DeviceGraph.from_csr(g, dev) for g in gs]
     plan = pkg.Plan(dgs, batch_lanes=2, grid_blocks=args.grid_blocks)
     single = pkg.Plan(dgs, grid_blocks=args.grid_blocks)
+    bt = plan.batch_tuning()
+    log(f"batch engine settings {bt}")
     qs = []
     for gi, g in enumerate(gs):
         for s in gg.pick_sources(g, 128, seed=0xC0FFEE00 + gi):
@@ -296,6 +298,8 @@ def run_batch(args):
         "latency_ms": {"p50": round(t_batch * 1e3, 3), "p99": round(t_batch * 1e3, 3),
                        "note": "one launch: every query completes with the batch"},
         "exact_vs_plain": exact,
+        "plan": {k: bt[k] for k in ("grid_blocks", "small_bin", "wave_bin", "chunk_edges",
+                                    "tuned_ms")},
     }
     plan.close()
     single.close()

@@ -310,6 +310,20 @@ bfs_status bfs_batch_poll(bfs_plan_t p, uint64_t *done, int32_t max, int32_t *n,
  * ticket, in submission order. */
 bfs_status bfs_batch_times(bfs_plan_t p, uint64_t ticket, int64_t *complete_ns, int32_t nq);
 
+/*
+ * Settings of the batched engine (host *out): grid_blocks of its cooperative
+ * level loop, the degree-bin tier thresholds small_bin / wave_bin and
+ * chunk_edges of its heavy tier, and tuned_ms, the best one-launch batch time
+ * the batch autotuner measured (0 when it did not run: autotune < 0, or 0 with
+ * fewer than 2^20 edges over all graphs). The autotuner runs inside
+ * bfs_plan_create, before any query, timing batches of batch_lanes * 64
+ * sources per graph whose outputs are discarded; options given explicitly
+ * (grid_blocks, small_bin, wave_bin, chunk_edges) are kept. loop_mode is
+ * BFS_LOOP_PERSISTENT; the other fields are 0. BFS_ERR_CAPACITY when the plan
+ * has no lane memory.
+ */
+bfs_status bfs_batch_tuning(bfs_plan_t p, bfs_tuning *out);
+
 #ifdef __cplusplus
 }
 #endif

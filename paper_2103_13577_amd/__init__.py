@@ -112,6 +112,7 @@ def lib():
         "bfs_batch_wait": (i32, [vp, u64, i64, ctypes.POINTER(bfs_batch_result)]),
         "bfs_batch_times": (i32, [vp, u64, vp, i32]),
         "bfs_batch_poll": (i32, [vp, vp, i32, ctypes.POINTER(i32), i64]),
+        "bfs_batch_tuning": (i32, [vp, ctypes.POINTER(bfs_tuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -124,7 +125,7 @@ def lib():
 EXPORTED = ("bfs_options_default", "bfs_workspace_size", "bfs_plan_create", "bfs_plan_destroy",
             "bfs_last_error", "bfs_run", "bfs_begin", "bfs_expand", "bfs_merge_frontier",
             "bfs_finish", "bfs_level_stats", "bfs_plan_tuning", "bfs_batch_submit",
-            "bfs_batch_wait", "bfs_batch_times", "bfs_batch_poll")
+            "bfs_batch_wait", "bfs_batch_times", "bfs_batch_poll", "bfs_batch_tuning")
 
 
 class BfsError(RuntimeError):
@@ -314,6 +315,12 @@ class Plan:
         """Settings the plan uses for one graph (after autotuning)."""
         t = bfs_tuning()
         self._check(lib().bfs_plan_tuning(self.h, graph, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in bfs_tuning._fields_}
+
+    def batch_tuning(self) -> dict:
+        """Settings of the batched engine (after the batch autotuner)."""
+        t = bfs_tuning()
+        self._check(lib().bfs_batch_tuning(self.h, ctypes.byref(t)))
         return {f: getattr(t, f) for f, _ in bfs_tuning._fields_}
 
     def level_stats(self):

@@ -84,6 +84,7 @@ struct BatchState {
   int64_t launches = 0, levels_total = 0;
   int32_t last_level = 0;       // global level clock of the engine
   bool streaming_mode = false;  // a streaming ticket was submitted
+  float tuned_ms = 0.f;         // batch autotuner: best one-launch batch time (0: not tuned)
 
   void run();
   bool step(std::unique_lock<std::mutex> &lk);
@@ -128,6 +129,115 @@ void layout_batch(const bfs_graph *g, int32_t ng, const bfs_options *o, WsLayout
   L.ms_depth_err = take(sizeof(uint64_t) * nslotw);
   L.ms_admit = take(sizeof(MsAdmit) * nslot);
   L.ms_mask = take(sizeof(uint64_t) * nslotw);
+}
+
+// Batch autotuner (plan creation, before the scheduler thread starts): times
+// one-launch batches of lw*64 sources per graph, outputs discarded, for a few
+// settings of the batched kernel -- grid size, then the degree-bin tier
+// thresholds, then the hub chunk size -- keeping each change only if it is
+// faster. Options given explicitly are not changed. Sources: vertices with an
+// edge among the first 2^16 of each graph (R-MAT labels are permuted).
+bfs_status batch_autotune(Plan *p, BatchState *b, int bpc) {
+  const int a = p->opt.autotune;
+  if (a < 0 || (a == 0 && p->lay.ms_mtot < (1ll << 20))) return BFS_OK;
+  const int per_graph = b->lw * 64;
+  std::vector<std::vector<int64_t>> srcs(b->ng);
+  for (int g = 0; g < b->ng; ++g) {
+    const bfs_graph &gr = p->graphs[g];
+    const int64_t cnt = std::min<int64_t>(gr.n_global, 1 << 16);
+    std::vector<int64_t> rp((size_t)cnt + 1);
+    hipError_t e = hipMemcpy(rp.data(), gr.row_ptr, sizeof(int64_t) * (cnt + 1), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return p->hip_fail(e, "batch autotune sources");
+    for (int64_t v = 0; v < cnt && (int)srcs[g].size() < per_graph; ++v)
+      if (rp[v + 1] > rp[v]) srcs[g].push_back(v);
+    if (srcs[g].empty()) srcs[g].push_back(0);
+  }
+  auto run_once = [&](float &ms) -> bfs_status {
+    const uint64_t tk = b->next_ticket++;
+    MsTicket &t = b->tickets[tk];
+    t.nq = b->ng * per_graph;
+    t.times.assign((size_t)t.nq, 0);
+    t.submit_ns = now_ns();
+    int idx = 0;
+    for (int g = 0; g < b->ng; ++g)
+      for (int k = 0; k < per_graph; ++k) {
+        MsQuery q;
+        q.graph = g;
+        q.type = 2;
+        q.src = srcs[g][(size_t)k % srcs[g].size()];
+        q.ticket = tk;
+        q.index_in_ticket = idx++;
+        b->pending[g].push_back(q);
+      }
+    std::unique_lock<std::mutex> lk(b->mu);
+    while (t.done < t.nq && b->step(lk)) {
+    }
+    const bool ok = t.done == t.nq && t.status == BFS_OK && b->worker_error.empty();
+    ms = (float)(t.complete_ns - t.submit_ns) * 1e-6f;
+    b->tickets.erase(tk);
+    b->completed.clear();
+    if (!ok) return p->fail(BFS_ERR_DEVICE, "batch autotune run failed: " + b->worker_error);
+    return BFS_OK;
+  };
+  struct Setting {
+    int grid, small_bin, wave_bin, chunk_shift;
+  };
+  auto apply = [&](const Setting &c) {
+    b->grid = c.grid;
+    b->view.small_bin = c.small_bin;
+    b->view.wave_bin = c.wave_bin;
+    b->view.chunk_shift = c.chunk_shift;
+  };
+  Setting best{b->grid, b->view.small_bin, b->view.wave_bin, b->view.chunk_shift};
+  float best_ms = 1e30f;
+  auto trial = [&](const Setting &c) -> bfs_status {
+    if (c.small_bin < 1 || c.wave_bin < c.small_bin || c.grid <= 0 || c.grid > bpc * p->num_cus ||
+        c.grid > kBarrierGroup * kBarrierMaxGroups)
+      return BFS_OK;
+    apply(c);
+    float warm = 0.f, ms = 0.f;
+    bfs_status s = run_once(warm);
+    if (s == BFS_OK && warm < 3.f * best_ms) s = run_once(ms);
+    else ms = warm;
+    if (s) return s;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+    apply(best);
+    return BFS_OK;
+  };
+  bfs_status s = trial(best);
+  const int cus = p->num_cus;
+  if (!s && p->opt.grid_blocks <= 0)
+    for (int g : {cus, 2 * cus, std::min(bpc, 8) * cus}) {
+      Setting c = best;
+      c.grid = g;
+      if ((s = trial(c))) break;
+    }
+  if (!s && p->opt.small_bin <= 0)
+    for (int sb : {4, 8}) {
+      Setting c = best;
+      c.small_bin = sb;
+      if ((s = trial(c))) break;
+    }
+  if (!s && p->opt.wave_bin <= 0)
+    for (int wb : {11, 15}) {
+      Setting c = best;
+      c.wave_bin = std::max(wb, c.small_bin);
+      if ((s = trial(c))) break;
+    }
+  if (!s && p->opt.chunk_edges <= 0)
+    for (int cs : {10, 12}) {
+      Setting c = best;
+      c.chunk_shift = cs;
+      if ((s = trial(c))) break;
+    }
+  apply(best);
+  b->tuned_ms = best_ms;
+  b->launches = 0;
+  b->levels_total = 0;
+  return s;
 }
 
 bfs_status batch_init(Plan *p) {
@@ -215,6 +325,12 @@ bfs_status batch_init(Plan *p) {
   }
   int bpc = ms_blocks_per_cu(lw);
   b->grid = p->opt.grid_blocks > 0 ? p->opt.grid_blocks : p->num_cus * std::min(std::max(bpc, 1), 4);
+  if (b->grid > kBarrierGroup * kBarrierMaxGroups) {
+    (void)hipHostFree(b->h_adm);
+    (void)hipHostFree(b->h_mask);
+    delete b;
+    return p->fail(BFS_ERR_ARG, "grid_blocks exceeds the grid barrier's 2048 blocks");
+  }
   if (bpc <= 0 || b->grid > bpc * p->num_cus || !p->coop) {
     (void)hipHostFree(b->h_adm);
     (void)hipHostFree(b->h_mask);
@@ -226,6 +342,14 @@ bfs_status batch_init(Plan *p) {
   b->active.assign((size_t)ng * lw, 0);
   b->dirty.assign((size_t)ng * lw, 0);
   p->batch = b;
+  bfs_status st = batch_autotune(p, b, bpc);
+  if (st) {
+    p->batch = nullptr;
+    (void)hipHostFree(b->h_adm);
+    (void)hipHostFree(b->h_mask);
+    delete b;
+    return st;
+  }
   b->worker = std::thread([b] { b->run(); });
   return BFS_OK;
 }
@@ -516,6 +640,23 @@ bfs_status bfs_batch_times(bfs_plan_t p, uint64_t ticket, int64_t *complete_ns, 
   const MsTicket &t = it->second;
   if (t.done < t.nq) return p->fail(BFS_ERR_STATE, "ticket not finished");
   for (int i = 0; i < std::min(nq, t.nq); ++i) complete_ns[i] = t.times[i];
+  return BFS_OK;
+}
+
+bfs_status bfs_batch_tuning(bfs_plan_t p, bfs_tuning *out) {
+  if (!p) return BFS_ERR_ARG;
+  if (!out) return p->fail(BFS_ERR_ARG, "NULL output");
+  BatchState *b = p->batch;
+  if (!b) return p->fail(BFS_ERR_CAPACITY, "plan has no lane memory for batched queries");
+  std::lock_guard<std::mutex> lk(b->mu);
+  *out = bfs_tuning{};
+  out->loop_mode = BFS_LOOP_PERSISTENT;
+  out->grid_blocks = b->grid;
+  out->small_bin = b->view.small_bin;
+  out->wave_bin = b->view.wave_bin;
+  out->chunk_edges = 1 << b->view.chunk_shift;
+  out->tuned_ms = b->tuned_ms;
+  out->direction = BFS_DIR_TOPDOWN;
   return BFS_OK;
 }
 

@@ -74,7 +74,7 @@ struct MsAdmit {
   int64_t src_local;
   int64_t n;      // vertices of the query's graph (output length)
   uint64_t out;   // device pointer of the output
-  int32_t type;   // 0 = uint8, 1 = int32
+  int32_t type;   // 0 = uint8, 1 = int32, 2 = discarded (the batch autotuner's timing runs)
   int32_t slot;   // (g*lw + l)*64 + b
 };
 

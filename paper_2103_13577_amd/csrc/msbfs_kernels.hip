@@ -220,10 +220,11 @@ __device__ __forceinline__ bool ms_update_vertex(const MsView &v, int L, bool va
         const int32_t val = L + 1 - v.slot_start[slot];
         const uint64_t ptr = v.slot_out[slot];
         // outputs are device memory: global stores, not generic (flat) ones
-        if (v.slot_type[slot] == 0) {
+        const int32_t type = v.slot_type[slot];
+        if (type == 0) {
           if (val > 254) atomic_or64(&v.depth_err[g * LW + l], 1ull << b);
           else ((__attribute__((address_space(1))) uint8_t *)ptr)[xl] = (uint8_t)val;
-        } else {
+        } else if (type == 1) {
           ((__attribute__((address_space(1))) int32_t *)ptr)[xl] = val;
         }
       }
@@ -455,6 +456,7 @@ __global__ void k_ms_flatten(const int64_t *rp_g, const int32_t *col_g, int64_t 
 // Output fill: 255 (uint8) or -1 (int32) everywhere; blockIdx.y = admission.
 __global__ void k_ms_fill(const MsAdmit *adm) {
   const MsAdmit a = adm[blockIdx.y];
+  if (a.type == 2) return;  // output discarded
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   if (a.type == 0) {
@@ -488,7 +490,7 @@ __global__ void k_ms_admit(MsView v, const MsAdmit *adm, int32_t nadm, int32_t l
   atomic_or64(&v.F[a.src_flat * LW + l], bit);
   atomic_or64(&v.S[a.src_flat * LW + l], bit);
   if (a.type == 0) ((uint8_t *)a.out)[a.src_local] = 0;
-  else ((int32_t *)a.out)[a.src_local] = 0;
+  else if (a.type == 1) ((int32_t *)a.out)[a.src_local] = 0;
   const uint32_t pos = atomic_add32(&v.ctl->nextra, 1u);
   v.extra[pos] = (int32_t)a.src_flat;
 }

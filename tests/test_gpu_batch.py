@@ -161,7 +161,9 @@ def test_full_size_batch_config(gpu):
     for gi, g in enumerate(gs):
         for s in gg.pick_sources(g, 128, seed=0xC0FFEE00 + gi):
             qs.append((gi, int(s), torch.empty(g.n, dtype=torch.uint8, device=gpu)))
-    print("[gpu] full batch submit", flush=True)
+    bt = plan.batch_tuning()
+    print(f"[gpu] full batch submit, batch tuning {bt}", flush=True)
+    assert bt["tuned_ms"] > 0 and bt["grid_blocks"] > 0  # above 2^20 edges the tuner runs
     t = plan.batch_submit(qs, pkg.BATCH_ONE_LAUNCH)
     plan.batch_wait(t)
     single = pkg.Plan(dgs)
@@ -173,3 +175,35 @@ def test_full_size_batch_config(gpu):
             assert np.array_equal(out.cpu().numpy(), _oracle_out(gs[gi], s, "u8")), (gi, s)
     single.close()
     plan.close()
+
+
+def test_batch_autotuner_leaves_lanes_clean(gpu):
+    """The batch autotuner (forced on a small union) times discarded-output
+    batches inside plan creation: queries afterwards are exact, an explicit
+    option is kept, autotune=-1 leaves it off, and a plan without lanes has no
+    batch settings."""
+    import torch
+    gs = _graphs_small()[:4]
+    dgs = [pkg.DeviceGraph.from_csr(g, gpu) for g in gs]
+    plan = pkg.Plan(dgs, batch_lanes=1, autotune=1, small_bin=5)
+    bt = plan.batch_tuning()
+    print(f"[gpu] batch tuning {bt}", flush=True)
+    assert bt["tuned_ms"] > 0 and bt["small_bin"] == 5 and bt["grid_blocks"] > 0
+    assert bt["chunk_edges"] in (1 << 10, 1 << 11, 1 << 12)
+    qs, refs = [], []
+    for gi, g in enumerate(gs):
+        for s in gg.pick_sources(g, 50, seed=2000 + gi):
+            qs.append((gi, int(s), torch.empty(g.n, dtype=torch.int32, device=gpu)))
+            refs.append(oracle.bfs(g, int(s)))
+    plan.batch_wait(plan.batch_submit(qs, pkg.BATCH_ONE_LAUNCH))
+    for (gi, s, out), ref in zip(qs, refs):
+        assert np.array_equal(out.cpu().numpy(), ref), (gi, s)
+    plan.close()
+    off = pkg.Plan(dgs, batch_lanes=1, autotune=-1)
+    assert off.batch_tuning()["tuned_ms"] == 0
+    off.close()
+    plain = pkg.Plan(dgs, autotune=-1)
+    with pytest.raises(pkg.BfsError) as e:
+        plain.batch_tuning()
+    assert e.value.status == 5
+    plain.close()
