@@ -520,6 +520,8 @@ def run_share29(args):
               for L in range(local.shape[0])]
     zeros = [torch.zeros(W, dtype=torch.int64, device=dev) for _ in range(inc.shape[1])]
     local_ref = local
+    inc_counts = [[int(np.sum(np.bitwise_count(inc[L, j]))) for j in range(inc.shape[1])]
+                  for L in range(local.shape[0])]
     del inc
     plan = pkg.Plan([dg])
     dist = torch.empty(g.n, dtype=torch.int32, device=dev)
@@ -562,9 +564,84 @@ def run_share29(args):
         total = t_begin.elapsed_time(ev[-1][2])
         return st, exp_ms, mrg_ms, total, ok
 
+    # Vertex-list form of the same messages: a staged message with fewer than
+    # n/32 vertices (4 bytes per vertex against n/8 bytes) goes as an ascending
+    # list, and the node exports its own global queue as a list when that is
+    # the smaller message (what it would send in the first round).
+    def to_list(words):
+        nz = torch.nonzero(words).flatten()
+        ar = torch.arange(64, device=dev, dtype=torch.int64)
+        out = []
+        for c0 in range(0, nz.numel(), 1 << 21):
+            w = nz[c0:c0 + (1 << 21)]
+            bits = ((words[w, None] >> ar) & 1).bool()
+            out.append((w[:, None] * 64 + ar)[bits])
+        return torch.cat(out).to(torch.int32) if out else torch.empty(0, dtype=torch.int32, device=dev)
+
+    list_cap = g.n // 32
+    lists = []
+    for L in range(len(staged)):
+        row = []
+        for j, m in enumerate(staged[L]):
+            row.append(to_list(m) if inc_counts[L][j] < list_cap else m)
+        lists.append(row)
+    sendbuf = torch.empty(max(list_cap, 1), dtype=torch.int32, device=dev)
+    n_list_msgs = sum(1 for row in lists for m in row if m.dtype == torch.int32)
+    log(f"list form: {n_list_msgs} of {sum(len(r) for r in lists)} staged messages go as lists")
+
+    def one_lists(check):
+        ev = []
+        t_begin = torch.cuda.Event(enable_timing=True)
+        t_begin.record()
+        plan.begin(0, src, dist)
+        L = 0
+        ok = True
+        sent_lists = 0
+        while True:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e2 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.expand()
+            e1.record()
+            try:
+                cnt = plan.frontier_list(sendbuf)
+                sent_lists += 1
+                if check:
+                    exp = local_ref[L] if L < local_ref.shape[0] else np.zeros(W, dtype=np.uint64)
+                    ok &= int(np.sum(np.bitwise_count(exp))) == cnt
+            except pkg.BfsError as err:
+                if err.status != 5:
+                    raise
+            row = lists[L] if L < len(lists) else zeros
+            ls = [m for m in row if m.dtype == torch.int32]
+            bms = [m for m in row if m.dtype != torch.int32]
+            if bms:
+                if ls:
+                    plan.merge_lists(ls, keep_next=True)
+                gnew, _ = plan.merge_frontier(bms)
+            else:
+                gnew, _ = plan.merge_lists(ls)
+            e2.record()
+            ev.append((e0, e1, e2))
+            if gnew == 0:
+                break
+            L += 1
+        plan.finish()
+        torch.cuda.synchronize()
+        exp_ms = [a.elapsed_time(bb) for a, bb, c in ev]
+        mrg_ms = [bb.elapsed_time(c) for a, bb, c in ev]
+        return exp_ms, mrg_ms, t_begin.elapsed_time(ev[-1][2]), ok, sent_lists
+
+    _, _, _, ok_l, _ = one_lists(check=True)
+    exact_lists = ok_l and np.array_equal(dist.cpu().numpy(), ref)
+    log(f"list form exact={exact_lists}")
+
     st, _, _, _, ok = one(check=True)
     exact = ok and np.array_equal(dist.cpu().numpy(), ref)
     runs = [one(check=False) for _ in range(max(args.steps if args.steps < 64 else 3, 1))]
+    runs_l = [one_lists(check=False) for _ in range(len(runs))]
+    tot_l = np.array([r[2] for r in runs_l])
     tot = np.array([r[3] for r in runs])
     exp_ms = np.mean([r[1] for r in runs], axis=0)
     mrg_ms = np.mean([r[2] for r in runs], axis=0)
@@ -587,6 +664,17 @@ def run_share29(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(mrg_gbs / HBM_PEAK_GBS, 4),
                      "traffic": None, "bytes_per_launch": int(merge_bytes)},
         "exact": bool(exact),
+        "list_messages": {
+            "note": "same traversal with every staged message of fewer than n/32 vertices sent as "
+                    "a vertex list (bfs_merge_lists) and the node's own global queue exported as a "
+                    "list when it is the smaller message (bfs_frontier_list); merge time includes "
+                    "the export",
+            "gteps": round(metrics.gteps(e_share, float(np.median(tot_l)) * 1e-3), 3),
+            "ms_per_step": round(float(np.median(tot_l)), 3),
+            "messages_as_lists": n_list_msgs, "exports_as_lists": int(runs_l[0][4]),
+            "per_level_ms": {"expand": [round(x, 3) for x in np.mean([r[0] for r in runs_l], axis=0)],
+                             "merge": [round(x, 3) for x in np.mean([r[1] for r in runs_l], axis=0)]},
+            "exact": bool(exact_lists)},
         "cpu_baseline": {"value": round(metrics.gteps(m_all, t_oracle), 4), "unit": "GTEPS",
                          "cores": 1, "kind": "oracle",
                          "sample": "the oracle's full traversal of the whole scale-29 graph "

@@ -235,7 +235,8 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
  *     global queue, for multi-round exchanges within a level; call again with
  *     the next round's messages) and does not advance the level; keep_next == 0
  *     finishes the level. *global_new and *owned_new (host, may be NULL)
- *     receive the counts for this call; reading them synchronises the stream.
+ *     receive the level's counts so far (every merge call of this level);
+ *     reading them synchronises the stream.
  *     The traversal is over when a finished level has global_new == 0
  *     (every node sees the same count after a full exchange).
  *   bfs_finish: writes parents (if parent != NULL) and fills *st.
@@ -245,6 +246,34 @@ bfs_status bfs_expand(bfs_plan_t p, const uint64_t **local_next);
 bfs_status bfs_merge_frontier(bfs_plan_t p, const uint64_t *const *incoming, int32_t k,
                               int32_t keep_next, int64_t *global_new, int64_t *owned_new);
 bfs_status bfs_finish(bfs_plan_t p, int32_t *parent, bfs_stats *st);
+
+/*
+ * Vertex-list messages (Section 3: in Phase 2 of Algorithm 2 the nodes send
+ * lists of active vertices; a list of c vertices takes 4c bytes against n/8
+ * for a bitmap, so it is the smaller message while c < n_global / 32).
+ *   bfs_frontier_list: after bfs_expand of the current level (and any
+ *     keep_next merges), writes the node's global queue -- the set bits of its
+ *     next-frontier bitmap -- as ascending int32 global ids into list (device,
+ *     capacity entries; may be NULL when capacity is 0) and the number of
+ *     vertices into *count (host). Synchronises the stream. When capacity >
+ *     0 and *count > capacity it returns BFS_ERR_CAPACITY, having written
+ *     only the first capacity ids; capacity 0 only counts (BFS_OK).
+ *   bfs_merge_lists: Phase 2 with k incoming lists: lists (host array of k
+ *     device pointers) and counts (host array of k entry counts, >= 0; a list
+ *     may be NULL when its count is 0). Each listed vertex absent from the
+ *     global queue is added to it, then the level is merged exactly as by
+ *     bfs_merge_frontier with the same keep_next: a list message and the same
+ *     set sent as a bitmap leave the same state, and the two forms can be
+ *     mixed within a level. Ids need not be sorted or distinct. An id outside
+ *     [0, n_global) is skipped and the call returns BFS_ERR_ARG (the
+ *     traversal must then restart with bfs_begin). *global_new and *owned_new
+ *     as for bfs_merge_frontier. Synchronises the stream.
+ * Both work in caller ids on traversals started by bfs_begin (BFS_ERR_STATE
+ * otherwise, or before bfs_expand of the level).
+ */
+bfs_status bfs_frontier_list(bfs_plan_t p, int32_t *list, int64_t capacity, int64_t *count);
+bfs_status bfs_merge_lists(bfs_plan_t p, const int32_t *const *lists, const int64_t *counts, int32_t k,
+                           int32_t keep_next, int64_t *global_new, int64_t *owned_new);
 
 /*
  * Per-level statistics of the last traversal (collect_stats must be set):

@@ -14,6 +14,8 @@ Functions and the passages they follow:
 * :func:`stage` -- per-level butterfly messages received by one compute node
   (Algorithm 2 Phase 1 sets X_c(L), exchanged along Figures 1/2).
 * :func:`merge` -- Algorithm 2 Phase 2 on bitmaps.
+* :func:`bitmap_list` -- a bitmap message as the ascending list of its
+  vertices (Section 3: Phase 2 exchanges lists of active vertices).
 * :func:`msbfs_u8` -- per-source BFS written as uint8 distances (255 means
   unreachable), for the batched multi-source path.
 * :mod:`oracle.butterfly_sim` -- a step-by-step simulation of Algorithm 2 with
@@ -141,6 +143,22 @@ def merge(n: int, level: int, next_bm: np.ndarray, incoming, visited: np.ndarray
                            dist.ctypes.data, v_begin, v_end, int(keep_next), q.ctypes.data,
                            ctypes.byref(owned))
     return int(tot), q[:owned.value].copy()
+
+
+def bitmap_list(bm: np.ndarray, n: int) -> np.ndarray:
+    """Ascending int32 ids v < n whose bit is set (vertex v is bit v & 63 of
+    uint64 word v >> 6): the vertex-list form of a butterfly message."""
+    words = np.ascontiguousarray(bm, dtype=np.uint64)
+    ids = []
+    for w in np.flatnonzero(words):
+        x = int(words[w])
+        b = 0
+        while x:
+            if x & 1 and 64 * int(w) + b < n:
+                ids.append(64 * int(w) + b)
+            x >>= 1
+            b += 1
+    return np.asarray(ids, dtype=np.int32)
 
 
 def msbfs_u8(g, sources) -> np.ndarray:

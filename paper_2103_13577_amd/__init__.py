@@ -113,6 +113,9 @@ def lib():
         "bfs_batch_times": (i32, [vp, u64, vp, i32]),
         "bfs_batch_poll": (i32, [vp, vp, i32, ctypes.POINTER(i32), i64]),
         "bfs_batch_tuning": (i32, [vp, ctypes.POINTER(bfs_tuning)]),
+        "bfs_frontier_list": (i32, [vp, vp, i64, ctypes.POINTER(i64)]),
+        "bfs_merge_lists": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), i32, i32,
+                                  ctypes.POINTER(i64), ctypes.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -125,7 +128,8 @@ def lib():
 EXPORTED = ("bfs_options_default", "bfs_workspace_size", "bfs_plan_create", "bfs_plan_destroy",
             "bfs_last_error", "bfs_run", "bfs_begin", "bfs_expand", "bfs_merge_frontier",
             "bfs_finish", "bfs_level_stats", "bfs_plan_tuning", "bfs_batch_submit",
-            "bfs_batch_wait", "bfs_batch_times", "bfs_batch_poll", "bfs_batch_tuning")
+            "bfs_batch_wait", "bfs_batch_times", "bfs_batch_poll", "bfs_batch_tuning",
+            "bfs_frontier_list", "bfs_merge_lists")
 
 
 class BfsError(RuntimeError):
@@ -303,6 +307,28 @@ class Plan:
         gn, on = ctypes.c_int64(0), ctypes.c_int64(0)
         self._check(lib().bfs_merge_frontier(self.h, arr, len(ptrs), int(keep_next),
                                              ctypes.byref(gn), ctypes.byref(on)))
+        return int(gn.value), int(on.value)
+
+    def frontier_list(self, out=None) -> int:
+        """The node's global queue as ascending int32 ids written into `out`
+        (device int32 tensor; None only counts). Returns the vertex count."""
+        cnt = ctypes.c_int64(0)
+        cap = 0 if out is None else out.numel()
+        self._check(lib().bfs_frontier_list(self.h, None if out is None else out.data_ptr(), cap,
+                                            ctypes.byref(cnt)))
+        return int(cnt.value)
+
+    def merge_lists(self, lists=(), keep_next: bool = False):
+        """Phase 2 over incoming vertex lists: (device int32 tensor, count)
+        pairs, or tensors whose length is the count. Returns (global_new,
+        owned_new) for the level so far."""
+        items = [(x, x.numel()) if not isinstance(x, tuple) else x for x in lists]
+        n = max(len(items), 1)
+        ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() if c > 0 else None for t, c in items])
+        cnts = (ctypes.c_int64 * n)(*[int(c) for _, c in items])
+        gn, on = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._check(lib().bfs_merge_lists(self.h, ptrs, cnts, len(items), int(keep_next),
+                                          ctypes.byref(gn), ctypes.byref(on)))
         return int(gn.value), int(on.value)
 
     def finish(self, parent=None) -> Stats:

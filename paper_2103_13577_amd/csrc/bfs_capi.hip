@@ -49,6 +49,7 @@ void layout_single(const bfs_graph *g, int32_t ng, WsLayout &L, size_t &off) {
   L.ctl = off; off = align_up(off + sizeof(Ctl), 256);
   L.lvl_frontier = off; off = align_up(off + sizeof(int64_t) * kMaxStatLevels, 256);
   L.lvl_hist = off; off = align_up(off + sizeof(uint32_t) * kMaxStatLevels * kNumBins, 256);
+  L.list_blk = off; off = align_up(off + sizeof(uint64_t) * (kListMaxBlocks + 1), 256);
   L.visited = off; off = align_up(off + sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), 256);
   L.next = off; off = align_up(off + sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), 256);
   L.front = off; off = align_up(off + sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), 256);
@@ -369,6 +370,63 @@ bfs_status bfs_merge_frontier(bfs_plan_t p, const uint64_t *const *incoming, int
       p->level += 1;
     }
   }
+  return BFS_OK;
+}
+
+bfs_status bfs_frontier_list(bfs_plan_t p, int32_t *list, int64_t capacity, int64_t *count) {
+  if (!p) return BFS_ERR_ARG;
+  if (!p->began || p->finished) return p->fail(BFS_ERR_STATE, "bfs_frontier_list before bfs_begin");
+  if (p->expanded_level != p->level)
+    return p->fail(BFS_ERR_STATE, "bfs_frontier_list before bfs_expand of this level");
+  if (!count) return p->fail(BFS_ERR_ARG, "count is NULL");
+  if (capacity < 0 || (capacity > 0 && !list)) return p->fail(BFS_ERR_ARG, "bad list or capacity");
+  if (p->cur_relabel) return p->fail(BFS_ERR_STATE, "the traversal runs on the relabelled copy");
+  View v = p->view(p->cur_graph, p->cur_dist);
+  uint64_t *blk = (uint64_t *)((char *)p->ws + p->lay.list_blk);
+  hipError_t e = launch_list_export(v.next, v.words, v.n, blk, list, capacity, p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "list export launch");
+  int nblk = 0;
+  int64_t per = 0;
+  list_geometry(v.words, nblk, per);
+  uint64_t total = 0;
+  e = hipMemcpyAsync(&total, blk + nblk, sizeof(total), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "list export count");
+  *count = (int64_t)total;
+  if (capacity > 0 && (int64_t)total > capacity)
+    return p->fail(BFS_ERR_CAPACITY, "the global queue holds " + std::to_string(total) +
+                                         " vertices, more than the list capacity " + std::to_string(capacity));
+  return BFS_OK;
+}
+
+bfs_status bfs_merge_lists(bfs_plan_t p, const int32_t *const *lists, const int64_t *counts, int32_t k,
+                           int32_t keep_next, int64_t *global_new, int64_t *owned_new) {
+  if (!p) return BFS_ERR_ARG;
+  if (!p->began || p->finished) return p->fail(BFS_ERR_STATE, "bfs_merge_lists before bfs_begin");
+  if (p->expanded_level != p->level)
+    return p->fail(BFS_ERR_STATE, "bfs_merge_lists before bfs_expand of this level");
+  if (k < 0 || (k > 0 && (!lists || !counts))) return p->fail(BFS_ERR_ARG, "bad incoming lists");
+  for (int i = 0; i < k; ++i) {
+    if (counts[i] < 0) return p->fail(BFS_ERR_ARG, "incoming list " + std::to_string(i) + " has a negative count");
+    if (counts[i] > 0 && !lists[i]) return p->fail(BFS_ERR_ARG, "incoming list " + std::to_string(i) + " is NULL");
+  }
+  if (p->cur_relabel) return p->fail(BFS_ERR_STATE, "the traversal runs on the relabelled copy");
+  View v = p->view(p->cur_graph, p->cur_dist);
+  for (int i = 0; i < k; ++i) {
+    hipError_t e = launch_list_scatter(lists[i], counts[i], v.next, v.n, &v.ctl->err, p->num_cus * 8, p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "list scatter launch");
+  }
+  const int L = p->level;
+  bfs_status st = bfs_merge_frontier(p, nullptr, 0, keep_next, nullptr, nullptr);
+  if (st) return st;
+  Ctl c;
+  st = p->read_ctl(c);
+  if (st) return st;
+  if (c.err & kErrListId)
+    return p->fail(BFS_ERR_ARG, "an incoming list holds a vertex id outside [0, n_global); the traversal "
+                                "must be restarted with bfs_begin");
+  if (global_new) *global_new = (int64_t)c.newcnt[L % 3];
+  if (owned_new) *owned_new = (int64_t)c.ownedcnt[L % 3];
   return BFS_OK;
 }
 

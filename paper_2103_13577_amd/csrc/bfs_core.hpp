@@ -19,6 +19,8 @@ constexpr uint32_t kBottomUpHot = 2048;       // frontier words a bottom-up bloc
 constexpr int64_t kDirAlpha = 14;  // top-down -> bottom-up when frontier edges * 14 > unvisited edges
 constexpr int64_t kDirBeta = 24;   // bottom-up -> top-down when frontier * 24 < n and shrinking
 constexpr int kMaxStatLevels = 4096;
+constexpr int kListMaxBlocks = 2048;  // blocks of the list export (count scratch: 2049 words)
+constexpr int32_t kErrListId = 4;     // Ctl::err bit: a received list held an id outside [0, n)
 constexpr int kHeavyShift = 40;  // packed heavy-tier counter: count << 40 | chunks
 constexpr uint64_t kChunkMask = (1ull << kHeavyShift) - 1;
 
@@ -116,5 +118,13 @@ int bottom_up_blocks_per_cu(uint32_t hot_words);
 size_t cu_lds_bytes(int64_t words);
 bool cu_fits(int64_t n, int64_t m, bool whole, int max_lds);
 hipError_t launch_bfs_cu(const View &v, int64_t src, int max_levels, hipStream_t s);
+// Vertex-list messages (frontier_list.hip). The export writes the set bits of
+// bm below n, ascending, into out[0..cap) and the total into blk[nblocks]
+// (blk: kListMaxBlocks + 1 words of scratch); with out NULL it only counts.
+void list_geometry(int64_t words, int &nblk, int64_t &per);
+hipError_t launch_list_export(const uint64_t *bm, int64_t words, int64_t n, uint64_t *blk, int32_t *out,
+                              int64_t cap, hipStream_t s);
+hipError_t launch_list_scatter(const int32_t *list, int64_t cnt, uint64_t *next, int64_t n, int32_t *err,
+                               int max_grid, hipStream_t s);
 
 }  // namespace bfsk

@@ -22,6 +22,7 @@ namespace bfsk {
 // Byte offsets of the workspace regions.
 struct WsLayout {
   size_t ctl, lvl_frontier, lvl_hist, visited, next, front;
+  size_t list_blk;  // uint64[kListMaxBlocks + 1]: block counts of the list export
   size_t q[3][kRing];
   size_t cstart[kRing];
   // batched multi-source state (see msbfs_core.hpp)

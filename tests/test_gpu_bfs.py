@@ -241,6 +241,150 @@ def test_partition_share_step_api(gpu, scale, P, radix, node):
     plan.close()
 
 
+@pytest.mark.parametrize("scale,P,radix,node,form", [(14, 16, 2, 0, "list"), (14, 16, 4, 0, "list"),
+                                                     (13, 16, 2, 7, "mixed"), (12, 4, 2, 3, "mixed"),
+                                                     (14, 16, 4, 5, "mixed")])
+def test_partition_share_list_messages(gpu, scale, P, radix, node, form):
+    """Phase 2 with vertex-list messages: at every level the exported global
+    queue equals the oracle's (ascending, after expansion and after each
+    butterfly round), and merging the staged messages as lists -- or as a mix
+    of lists (unsorted, with duplicates) and bitmaps -- gives the oracle's
+    counts and distances."""
+    import torch
+    g = gg.rmat(scale, 8, seed=100 + scale, perm_seed=200 + scale)
+    src = int(gg.pick_sources(g, 1, seed=300 + scale)[0])
+    ref = oracle.bfs(g, src)
+    b = gg.partition_1d(g.row_ptr, P)
+    local, inc = oracle.stage(g, ref, b, node, radix)
+    nlev = local.shape[0]
+    dg = pkg.DeviceGraph.from_csr(g, gpu, int(b[node]), int(b[node + 1]))
+    plan = pkg.Plan([dg])
+    dist = torch.empty(g.n, dtype=torch.int32, device=gpu)
+    buf = torch.empty(g.n, dtype=torch.int32, device=gpu)
+    W = (g.n + 63) // 64
+    zeros = np.zeros(W, dtype=np.uint64)
+    per_round = radix - 1
+    depth = inc.shape[1] // per_round
+    rng = np.random.default_rng(scale * 31 + node)
+    plan.begin(0, src, dist)
+    L = 0
+    while True:
+        plan.expand()
+        have = (local[L] if L < nlev else zeros).copy()
+        cnt = plan.frontier_list(buf)
+        assert cnt == plan.frontier_list()
+        assert np.array_equal(buf[:cnt].cpu().numpy(), oracle.bitmap_list(have, g.n)), f"level {L}"
+        for i in range(depth):
+            last = i == depth - 1
+            lists, bms = [], []
+            for j in range(per_round):
+                m = inc[L, i * per_round + j] if L < nlev else zeros
+                have |= m
+                ids = oracle.bitmap_list(m, g.n)
+                as_list = form == "list" or (i + j + L) % 2 == 0
+                if as_list:
+                    if form == "mixed" and ids.size:
+                        ids = np.concatenate([ids, ids[: min(3, ids.size)]])
+                        rng.shuffle(ids)
+                    lists.append(torch.from_numpy(ids).to(gpu))
+                else:
+                    bms.append(_words_to_tensor(m, gpu))
+            if bms:
+                if lists:
+                    plan.merge_lists(lists, keep_next=True)
+                gnew, onew = plan.merge_frontier(bms, keep_next=not last)
+            else:
+                gnew, onew = plan.merge_lists(lists, keep_next=not last)
+            if not last:
+                cnt = plan.frontier_list(buf)
+                assert np.array_equal(buf[:cnt].cpu().numpy(), oracle.bitmap_list(have, g.n)), (L, i)
+        assert gnew == int((ref == L + 1).sum())
+        assert onew == int((ref == L + 1)[b[node]:b[node + 1]].sum())
+        if gnew == 0:
+            break
+        L += 1
+    st = plan.finish()
+    assert st.levels == L + 1 == ref.max() + 1
+    assert np.array_equal(dist.cpu().numpy(), ref)
+    plan.close()
+
+
+def test_list_message_errors(gpu):
+    """Capacity too small, ids out of range, negative counts and wrong call
+    order are reported by status; the plan stays usable."""
+    import torch
+    g = gg.rmat(12, 8, seed=77, perm_seed=78)
+    src = int(gg.pick_sources(g, 1, seed=79)[0])
+    ref = oracle.bfs(g, src)
+    plan = pkg.Plan([pkg.DeviceGraph.from_csr(g, gpu)], autotune=-1)
+    dist = torch.empty(g.n, dtype=torch.int32, device=gpu)
+    with pytest.raises(pkg.BfsError) as e:
+        plan.frontier_list()
+    assert e.value.status == 7
+    plan.begin(0, src, dist)
+    with pytest.raises(pkg.BfsError) as e:
+        plan.frontier_list()
+    assert e.value.status == 7  # before bfs_expand of the level
+    plan.expand()
+    level1 = np.flatnonzero(ref == 1).astype(np.int32)
+    assert plan.frontier_list() == level1.size > 2
+    small = torch.full((2,), -7, dtype=torch.int32, device=gpu)
+    with pytest.raises(pkg.BfsError) as e:
+        plan.frontier_list(small)
+    assert e.value.status == 5
+    assert np.array_equal(small.cpu().numpy(), level1[:2])
+    h = pkg.lib()
+    ptrs = (ctypes.c_void_p * 1)(None)
+    cnts = (ctypes.c_int64 * 1)(-1)
+    assert h.bfs_merge_lists(plan.h, ptrs, cnts, 1, 0, None, None) == 1  # negative count
+    cnts[0] = 3
+    assert h.bfs_merge_lists(plan.h, ptrs, cnts, 1, 0, None, None) == 1  # NULL list
+    bad = torch.tensor([int(level1[0]), g.n], dtype=torch.int32, device=gpu)
+    with pytest.raises(pkg.BfsError) as e:
+        plan.merge_lists([bad])
+    assert e.value.status == 1
+    # a fresh traversal with list-form (empty) messages equals the oracle
+    plan.begin(0, src, dist)
+    while True:
+        plan.expand()
+        gnew, _ = plan.merge_lists([])
+        if gnew == 0:
+            break
+    plan.finish()
+    assert np.array_equal(dist.cpu().numpy(), ref)
+    plan.run(0, src, dist=dist)  # the relabelled copy is not exported
+    with pytest.raises(pkg.BfsError) as e:
+        plan.frontier_list()
+    assert e.value.status == 7
+    plan.close()
+
+
+def test_list_export_many_blocks(gpu):
+    """2^25 + 1000 vertices (1025 export blocks of 512 bitmap words, a ragged
+    last word): a star whose 3000 leaves are spread over the whole id range."""
+    import torch
+    n = (1 << 25) + 1000
+    leaves = np.unique((np.arange(1, 3001, dtype=np.int64) * 11184811 + 977) % (n - 1) + 1)
+    leaves = np.union1d(leaves, [n - 1, 64, 63])
+    edges = np.stack([np.zeros(leaves.size, dtype=np.int64), leaves], axis=1)
+    g = gg.from_edges(n, edges, "spread star")
+    plan = pkg.Plan([pkg.DeviceGraph.from_csr(g, gpu)], autotune=-1)
+    dist = torch.empty(n, dtype=torch.int32, device=gpu)
+    buf = torch.empty(leaves.size + 5, dtype=torch.int32, device=gpu)
+    plan.begin(0, 0, dist)
+    plan.expand()
+    cnt = plan.frontier_list(buf)
+    assert cnt == leaves.size
+    assert np.array_equal(buf[:cnt].cpu().numpy(), leaves.astype(np.int32))
+    gnew, onew = plan.merge_lists([buf[:cnt]])
+    assert gnew == onew == leaves.size
+    leaf = int(leaves[-1])
+    plan.begin(0, leaf, dist)
+    plan.expand()
+    assert plan.frontier_list(buf) == 1 and int(buf[0]) == 0
+    plan.close()
+
+
 def _read_device_words(addr, W, gpu):
     """Copies W uint64 words at a raw device address to the host (hipMemcpy)."""
     import torch

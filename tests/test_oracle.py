@@ -380,3 +380,44 @@ def test_msbfs_u8():
     out = oracle.msbfs_u8(g, [0, 6])
     assert np.array_equal(out[0], [0, 1, 2, 3, 4, 255, 255, 255])
     assert np.array_equal(out[1], [255] * 5 + [1, 0, 1])
+
+
+# ---------------------------------------------------------------------------
+# vertex-list messages
+# ---------------------------------------------------------------------------
+
+def test_bitmap_list_fixture():
+    """Vertex v is bit v & 63 of word v >> 6; the list is ascending and stops
+    below n."""
+    words = np.array([1 | (1 << 5) | (1 << 63), 1, 1 << 2], dtype=np.uint64)
+    assert oracle.bitmap_list(words, 131).tolist() == [0, 5, 63, 64, 130]
+    assert oracle.bitmap_list(words, 130).tolist() == [0, 5, 63, 64]
+    assert oracle.bitmap_list(np.zeros(4, dtype=np.uint64), 256).size == 0
+
+
+def test_bitmap_list_round_trip():
+    rng = np.random.default_rng(11)
+    for n in (1, 63, 64, 65, 1000, 4097):
+        W = (n + 63) // 64
+        ids = np.unique(rng.integers(0, n, size=max(n // 7, 1)))
+        bm = np.zeros(W, dtype=np.uint64)
+        for v in ids:
+            bm[v >> 6] |= np.uint64(1) << np.uint64(v & 63)
+        assert np.array_equal(oracle.bitmap_list(bm, n), ids.astype(np.int32))
+
+
+@pytest.mark.parametrize("radix", [2, 4])
+def test_stage_lists_match_algorithm2_queues(radix):
+    """The list form of every staged message equals, in ascending order, the
+    global queue the step-by-step simulation of Algorithm 2 copied."""
+    g = gg.rmat(10, 8, seed=60, perm_seed=61)
+    src = int(gg.pick_sources(g, 1, seed=62)[0])
+    d = oracle.bfs(g, src)
+    b = gg.partition_1d(g.row_ptr, 16)
+    _, rec = bs.simulate(g, src, b, radix, 0)
+    local, inc = oracle.stage(g, d, b, 0, radix)
+    for L, r in enumerate(rec):
+        assert oracle.bitmap_list(local[L], g.n).tolist() == sorted(r["local"])
+        flat = [s for rnd in r["rounds"] for s in rnd]
+        for j, s in enumerate(flat):
+            assert oracle.bitmap_list(inc[L, j], g.n).tolist() == sorted(s)
