@@ -585,6 +585,12 @@ def run_share29(args):
         for j, m in enumerate(staged[L]):
             row.append(to_list(m) if inc_counts[L][j] < list_cap else m)
         lists.append(row)
+    # bytes the node receives per level in each form (each staged message as
+    # a bitmap of W words, or in the list form as 4 bytes per vertex when that
+    # is smaller)
+    bm_bytes = [8 * W * len(row) for row in lists]
+    mixed_bytes = [sum(4 * inc_counts[L][j] if m.dtype == torch.int32 else 8 * W
+                       for j, m in enumerate(row)) for L, row in enumerate(lists)]
     sendbuf = torch.empty(max(list_cap, 1), dtype=torch.int32, device=dev)
     n_list_msgs = sum(1 for row in lists for m in row if m.dtype == torch.int32)
     log(f"list form: {n_list_msgs} of {sum(len(r) for r in lists)} staged messages go as lists")
@@ -616,12 +622,7 @@ def run_share29(args):
             row = lists[L] if L < len(lists) else zeros
             ls = [m for m in row if m.dtype == torch.int32]
             bms = [m for m in row if m.dtype != torch.int32]
-            if bms:
-                if ls:
-                    plan.merge_lists(ls, keep_next=True)
-                gnew, _ = plan.merge_frontier(bms)
-            else:
-                gnew, _ = plan.merge_lists(ls)
+            gnew, _ = plan.merge_lists(ls, bitmaps=bms)
             e2.record()
             ev.append((e0, e1, e2))
             if gnew == 0:
@@ -672,6 +673,7 @@ def run_share29(args):
             "gteps": round(metrics.gteps(e_share, float(np.median(tot_l)) * 1e-3), 3),
             "ms_per_step": round(float(np.median(tot_l)), 3),
             "messages_as_lists": n_list_msgs, "exports_as_lists": int(runs_l[0][4]),
+            "received_bytes_per_level": {"bitmaps": bm_bytes, "lists_where_smaller": mixed_bytes},
             "per_level_ms": {"expand": [round(x, 3) for x in np.mean([r[0] for r in runs_l], axis=0)],
                              "merge": [round(x, 3) for x in np.mean([r[1] for r in runs_l], axis=0)]},
             "exact": bool(exact_lists)},

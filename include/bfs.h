@@ -258,22 +258,26 @@ bfs_status bfs_finish(bfs_plan_t p, int32_t *parent, bfs_stats *st);
  *     vertices into *count (host). Synchronises the stream. When capacity >
  *     0 and *count > capacity it returns BFS_ERR_CAPACITY, having written
  *     only the first capacity ids; capacity 0 only counts (BFS_OK).
- *   bfs_merge_lists: Phase 2 with k incoming lists: lists (host array of k
- *     device pointers) and counts (host array of k entry counts, >= 0; a list
- *     may be NULL when its count is 0). Each listed vertex absent from the
- *     global queue is added to it, then the level is merged exactly as by
- *     bfs_merge_frontier with the same keep_next: a list message and the same
- *     set sent as a bitmap leave the same state, and the two forms can be
- *     mixed within a level. Ids need not be sorted or distinct. An id outside
- *     [0, n_global) is skipped and the call returns BFS_ERR_ARG (the
- *     traversal must then restart with bfs_begin). *global_new and *owned_new
- *     as for bfs_merge_frontier. Synchronises the stream.
+ *   bfs_merge_lists: Phase 2 with k incoming lists and kb incoming bitmaps
+ *     in one pass: lists (host array of k device pointers) and counts (host
+ *     array of k entry counts, >= 0; a list may be NULL when its count is 0),
+ *     bitmaps as for bfs_merge_frontier (may be NULL when kb is 0). Each
+ *     listed vertex absent from the global queue is added to it, then the
+ *     level is merged exactly as by bfs_merge_frontier(bitmaps, kb,
+ *     keep_next): a list message and the same set sent as a bitmap leave the
+ *     same state, and the forms can be mixed within a call and a level. Ids
+ *     need not be sorted or distinct. An id outside [0, n_global) is skipped
+ *     and flagged; the first merge call that reads the level's counts (one
+ *     with keep_next == 0, or with global_new or owned_new non-NULL) then
+ *     returns BFS_ERR_ARG, and the traversal must restart with bfs_begin.
+ *     *global_new and *owned_new as for bfs_merge_frontier.
  * Both work in caller ids on traversals started by bfs_begin (BFS_ERR_STATE
  * otherwise, or before bfs_expand of the level).
  */
 bfs_status bfs_frontier_list(bfs_plan_t p, int32_t *list, int64_t capacity, int64_t *count);
 bfs_status bfs_merge_lists(bfs_plan_t p, const int32_t *const *lists, const int64_t *counts, int32_t k,
-                           int32_t keep_next, int64_t *global_new, int64_t *owned_new);
+                           const uint64_t *const *bitmaps, int32_t kb, int32_t keep_next,
+                           int64_t *global_new, int64_t *owned_new);
 
 /*
  * Per-level statistics of the last traversal (collect_stats must be set):

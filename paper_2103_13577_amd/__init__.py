@@ -114,8 +114,9 @@ def lib():
         "bfs_batch_poll": (i32, [vp, vp, i32, ctypes.POINTER(i32), i64]),
         "bfs_batch_tuning": (i32, [vp, ctypes.POINTER(bfs_tuning)]),
         "bfs_frontier_list": (i32, [vp, vp, i64, ctypes.POINTER(i64)]),
-        "bfs_merge_lists": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), i32, i32,
-                                  ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "bfs_merge_lists": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), i32,
+                                  ctypes.POINTER(vp), i32, i32, ctypes.POINTER(i64),
+                                  ctypes.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -318,17 +319,19 @@ class Plan:
                                             ctypes.byref(cnt)))
         return int(cnt.value)
 
-    def merge_lists(self, lists=(), keep_next: bool = False):
-        """Phase 2 over incoming vertex lists: (device int32 tensor, count)
-        pairs, or tensors whose length is the count. Returns (global_new,
-        owned_new) for the level so far."""
+    def merge_lists(self, lists=(), bitmaps=(), keep_next: bool = False):
+        """Phase 2 over incoming vertex lists -- (device int32 tensor, count)
+        pairs, or tensors whose length is the count -- and bitmaps, in one
+        pass. Returns (global_new, owned_new) for the level so far."""
         items = [(x, x.numel()) if not isinstance(x, tuple) else x for x in lists]
         n = max(len(items), 1)
         ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() if c > 0 else None for t, c in items])
         cnts = (ctypes.c_int64 * n)(*[int(c) for _, c in items])
+        bps = [x if isinstance(x, int) else x.data_ptr() for x in bitmaps]
+        barr = (ctypes.c_void_p * max(len(bps), 1))(*bps)
         gn, on = ctypes.c_int64(0), ctypes.c_int64(0)
-        self._check(lib().bfs_merge_lists(self.h, ptrs, cnts, len(items), int(keep_next),
-                                          ctypes.byref(gn), ctypes.byref(on)))
+        self._check(lib().bfs_merge_lists(self.h, ptrs, cnts, len(items), barr, len(bps),
+                                          int(keep_next), ctypes.byref(gn), ctypes.byref(on)))
         return int(gn.value), int(on.value)
 
     def finish(self, parent=None) -> Stats:

@@ -356,6 +356,9 @@ bfs_status bfs_merge_frontier(bfs_plan_t p, const uint64_t *const *incoming, int
     Ctl c;
     bfs_status st = p->read_ctl(c);
     if (st) return st;
+    if (c.err & kErrListId)
+      return p->fail(BFS_ERR_ARG, "an incoming list held a vertex id outside [0, n_global); the "
+                                  "traversal must be restarted with bfs_begin");
     if (global_new) *global_new = (int64_t)c.newcnt[p->level % 3];
     if (owned_new) *owned_new = (int64_t)c.ownedcnt[p->level % 3];
     if (!keep_next) {
@@ -400,34 +403,28 @@ bfs_status bfs_frontier_list(bfs_plan_t p, int32_t *list, int64_t capacity, int6
 }
 
 bfs_status bfs_merge_lists(bfs_plan_t p, const int32_t *const *lists, const int64_t *counts, int32_t k,
-                           int32_t keep_next, int64_t *global_new, int64_t *owned_new) {
+                           const uint64_t *const *bitmaps, int32_t kb, int32_t keep_next,
+                           int64_t *global_new, int64_t *owned_new) {
   if (!p) return BFS_ERR_ARG;
   if (!p->began || p->finished) return p->fail(BFS_ERR_STATE, "bfs_merge_lists before bfs_begin");
   if (p->expanded_level != p->level)
     return p->fail(BFS_ERR_STATE, "bfs_merge_lists before bfs_expand of this level");
   if (k < 0 || (k > 0 && (!lists || !counts))) return p->fail(BFS_ERR_ARG, "bad incoming lists");
+  if (kb < 0 || (kb > 0 && !bitmaps)) return p->fail(BFS_ERR_ARG, "bad incoming bitmaps");
   for (int i = 0; i < k; ++i) {
     if (counts[i] < 0) return p->fail(BFS_ERR_ARG, "incoming list " + std::to_string(i) + " has a negative count");
     if (counts[i] > 0 && !lists[i]) return p->fail(BFS_ERR_ARG, "incoming list " + std::to_string(i) + " is NULL");
   }
+  for (int i = 0; i < kb; ++i)
+    if (!bitmaps[i]) return p->fail(BFS_ERR_ARG, "incoming bitmap " + std::to_string(i) + " is NULL");
   if (p->cur_relabel) return p->fail(BFS_ERR_STATE, "the traversal runs on the relabelled copy");
   View v = p->view(p->cur_graph, p->cur_dist);
   for (int i = 0; i < k; ++i) {
     hipError_t e = launch_list_scatter(lists[i], counts[i], v.next, v.n, &v.ctl->err, p->num_cus * 8, p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "list scatter launch");
   }
-  const int L = p->level;
-  bfs_status st = bfs_merge_frontier(p, nullptr, 0, keep_next, nullptr, nullptr);
-  if (st) return st;
-  Ctl c;
-  st = p->read_ctl(c);
-  if (st) return st;
-  if (c.err & kErrListId)
-    return p->fail(BFS_ERR_ARG, "an incoming list holds a vertex id outside [0, n_global); the traversal "
-                                "must be restarted with bfs_begin");
-  if (global_new) *global_new = (int64_t)c.newcnt[L % 3];
-  if (owned_new) *owned_new = (int64_t)c.ownedcnt[L % 3];
-  return BFS_OK;
+  // one merge pass over the listed vertices (now in the global queue) and the bitmaps
+  return bfs_merge_frontier(p, bitmaps, kb, keep_next, global_new, owned_new);
 }
 
 namespace {

@@ -500,6 +500,9 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
       om = nw & owned_mask(w, v.vb, v.ve);
     }
     my_new += (uint64_t)__popcll(nw);
+    // A workgroup step without new vertices (the common case on sparse
+    // levels) has no distances, queue entries or counters to write.
+    if (!__syncthreads_or(nw != 0ull)) continue;
 
     // Pass 1: distances of new vertices; degree tier of owned new vertices.
     // Words are taken four at a time (lanes = the 64 bits of a word) so the
@@ -507,6 +510,19 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
     uint64_t t1m = 0, t2m = 0;
     uint64_t chunks = 0;  // wave-uniform
     uint64_t act = ballot(nw != 0);
+    if (ballot(om != 0) == 0ull) {
+      // no owned new vertex in this wavefront's words (a node's share covers
+      // a fraction of the bitmap): distances only, one word per step
+      while (act) {
+        const int j = __ffsll((unsigned long long)act) - 1;
+        act &= act - 1;
+        const uint64_t wj = readlane64(nw, j);
+        if ((wj >> lane) & 1ull) {
+          const int64_t vtx = (wbase + j) * 64 + lane;
+          dist[v.old_id ? (int64_t)v.old_id[vtx] : vtx] = dnew;
+        }
+      }
+    }
     while (act) {
       constexpr int kW = 4;
       int js[kW];

@@ -289,12 +289,12 @@ def test_partition_share_list_messages(gpu, scale, P, radix, node, form):
                     lists.append(torch.from_numpy(ids).to(gpu))
                 else:
                     bms.append(_words_to_tensor(m, gpu))
-            if bms:
+            if bms and L % 2:  # the two forms in separate calls of one round
                 if lists:
                     plan.merge_lists(lists, keep_next=True)
                 gnew, onew = plan.merge_frontier(bms, keep_next=not last)
-            else:
-                gnew, onew = plan.merge_lists(lists, keep_next=not last)
+            else:  # one pass over both forms
+                gnew, onew = plan.merge_lists(lists, bitmaps=bms, keep_next=not last)
             if not last:
                 cnt = plan.frontier_list(buf)
                 assert np.array_equal(buf[:cnt].cpu().numpy(), oracle.bitmap_list(have, g.n)), (L, i)
@@ -336,10 +336,21 @@ def test_list_message_errors(gpu):
     h = pkg.lib()
     ptrs = (ctypes.c_void_p * 1)(None)
     cnts = (ctypes.c_int64 * 1)(-1)
-    assert h.bfs_merge_lists(plan.h, ptrs, cnts, 1, 0, None, None) == 1  # negative count
+    assert h.bfs_merge_lists(plan.h, ptrs, cnts, 1, None, 0, 0, None, None) == 1  # negative count
     cnts[0] = 3
-    assert h.bfs_merge_lists(plan.h, ptrs, cnts, 1, 0, None, None) == 1  # NULL list
+    assert h.bfs_merge_lists(plan.h, ptrs, cnts, 1, None, 0, 0, None, None) == 1  # NULL list
+    assert h.bfs_merge_lists(plan.h, None, None, 0, None, 2, 0, None, None) == 1  # NULL bitmaps
     bad = torch.tensor([int(level1[0]), g.n], dtype=torch.int32, device=gpu)
+    ptrs[0] = bad.data_ptr()
+    cnts[0] = 2
+    # keep_next with no counts requested: the bad id is flagged, reported by
+    # the call that finishes the level
+    assert h.bfs_merge_lists(plan.h, ptrs, cnts, 1, None, 0, 1, None, None) == 0
+    with pytest.raises(pkg.BfsError) as e:
+        plan.merge_frontier([])
+    assert e.value.status == 1
+    plan.begin(0, src, dist)
+    plan.expand()
     with pytest.raises(pkg.BfsError) as e:
         plan.merge_lists([bad])
     assert e.value.status == 1
