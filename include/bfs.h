@@ -243,6 +243,22 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
  */
 bfs_status bfs_begin(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist);
 bfs_status bfs_expand(bfs_plan_t p, const uint64_t **local_next);
+/*
+ * Phase 1 as a bottom-up step (Section 3: the butterfly exchange works as
+ * well with bottom-up or direction-optimizing traversals): every unvisited
+ * owned vertex scans its adjacency until it meets a vertex of the level's
+ * frontier and, if it does, is marked in the node's next-frontier bitmap.
+ * The frontier is the whole level over all n_global vertices -- on a share,
+ * the merged result of the previous level's exchange -- so the local bitmap
+ * holds exactly the owned vertices of the next level. *local_next as for
+ * bfs_expand; bfs_merge_frontier / bfs_merge_lists finish the level as after
+ * bfs_expand, and the two expansions can alternate level by level (the
+ * caller chooses the direction; every node must choose the same). Needs a
+ * plan created with direction = BFS_DIR_OPTIMIZING (its merges then also
+ * keep the level's frontier bitmap) and a traversal started by bfs_begin;
+ * BFS_ERR_STATE otherwise, or when the previous level was not finished.
+ */
+bfs_status bfs_expand_bottom_up(bfs_plan_t p, const uint64_t **local_next);
 bfs_status bfs_merge_frontier(bfs_plan_t p, const uint64_t *const *incoming, int32_t k,
                               int32_t keep_next, int64_t *global_new, int64_t *owned_new);
 bfs_status bfs_finish(bfs_plan_t p, int32_t *parent, bfs_stats *st);

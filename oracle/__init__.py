@@ -16,6 +16,9 @@ Functions and the passages they follow:
 * :func:`merge` -- Algorithm 2 Phase 2 on bitmaps.
 * :func:`bitmap_list` -- a bitmap message as the ascending list of its
   vertices (Section 3: Phase 2 exchanges lists of active vertices).
+* :func:`stage_bottom_up` -- the butterfly messages of a level whose Phase 1
+  is a bottom-up step (Section 3 allows bottom-up traversals behind the same
+  exchange): each node finds exactly its owned vertices of the next level.
 * :func:`msbfs_u8` -- per-source BFS written as uint8 distances (255 means
   unreachable), for the batched multi-source path.
 * :mod:`oracle.butterfly_sim` -- a step-by-step simulation of Algorithm 2 with
@@ -159,6 +162,53 @@ def bitmap_list(bm: np.ndarray, n: int) -> np.ndarray:
             x >>= 1
             b += 1
     return np.asarray(ids, dtype=np.int32)
+
+
+def stage_bottom_up(n: int, dist: np.ndarray, bounds: np.ndarray, node: int = 0, radix: int = 2):
+    """Butterfly inputs for compute node ``node`` when Phase 1 of every level
+    is a bottom-up step, in the layout of :func:`stage`.
+
+    A bottom-up step of node c marks every unvisited vertex it owns that has a
+    neighbour in the level-L frontier, which is every owned vertex at distance
+    L+1, so X_c(L) = {u owned by c : d[u] = L+1}. In round i the partner that
+    differs from ``node`` in base-radix digit i sends the union of X_c over its
+    aligned block of radix^i nodes (the queues it has merged so far).
+    """
+    P = len(bounds) - 1
+    depth, pw = 0, 1
+    while pw < P:
+        pw *= radix
+        depth += 1
+    if pw != P:
+        raise ValueError("P must be a power of the radix")
+    K = depth * (radix - 1)
+    nlev = int(max(int(dist.max()), 0))
+    W = (n + 63) // 64
+    owner = np.searchsorted(np.asarray(bounds, dtype=np.int64), np.arange(n), side="right") - 1
+
+    def bitmap(mask):
+        bm = np.zeros(W, dtype=np.uint64)
+        ids = np.flatnonzero(mask).astype(np.uint64)
+        np.bitwise_or.at(bm, (ids >> np.uint64(6)).astype(np.int64), np.uint64(1) << (ids & np.uint64(63)))
+        return bm
+
+    local = np.zeros((nlev, W), dtype=np.uint64)
+    inc = np.zeros((nlev, K, W), dtype=np.uint64)
+    for L in range(nlev):
+        lev = dist == L + 1
+        local[L] = bitmap(lev & (owner == node))
+        k = 0
+        for i in range(depth):
+            step = radix ** i
+            digit = (node // step) % radix
+            for j in range(radix):
+                if j == digit:
+                    continue
+                partner = node + (j - digit) * step
+                lo = (partner // step) * step  # the partner's block of radix^i nodes
+                inc[L, k] = bitmap(lev & (owner >= lo) & (owner < lo + step))
+                k += 1
+    return local, inc
 
 
 def msbfs_u8(g, sources) -> np.ndarray:

@@ -42,8 +42,12 @@ def message_count(P: int, radix: int) -> int:
     return P * (radix - 1) * depth
 
 
-def simulate(g, root: int, bounds, radix: int = 2, record_node: int = 0):
-    """Run Algorithm 2 with P = len(bounds)-1 nodes.
+def simulate(g, root: int, bounds, radix: int = 2, record_node: int = 0, bottom_up_levels=()):
+    """Run Algorithm 2 with P = len(bounds)-1 nodes. Levels listed in
+    ``bottom_up_levels`` run Phase 1 bottom-up: each node checks every vertex
+    it owns that it has not reached and takes it when one of its neighbours
+    is in the level's frontier (every node holds all distances, so it knows
+    the frontier).
 
     Returns (d_local, records) where d_local is int32[P, n] (-1 = infinity) and
     records[L] = {"local": set X_record_node(L),
@@ -74,6 +78,18 @@ def simulate(g, root: int, bounds, radix: int = 2, record_node: int = 0):
         in_global = [set() for _ in range(P)]
         q_next = [[] for _ in range(P)]
         for c in range(P):
+            if level in bottom_up_levels:
+                for v in range(int(bounds[c]), int(bounds[c + 1])):
+                    if d_local[c][v] != INF:
+                        continue
+                    for e in range(rp[v], rp[v + 1]):
+                        if d_local[c][int(col[e])] == level:
+                            in_global[c].add(v)
+                            q_global[c].append(v)
+                            d_local[c][v] = level + 1
+                            q_next[c].append(v)
+                            break
+                continue
             for v in q_local[c]:
                 for e in range(rp[v], rp[v + 1]):
                     u = int(col[e])

@@ -114,6 +114,7 @@ def lib():
         "bfs_batch_poll": (i32, [vp, vp, i32, ctypes.POINTER(i32), i64]),
         "bfs_batch_tuning": (i32, [vp, ctypes.POINTER(bfs_tuning)]),
         "bfs_frontier_list": (i32, [vp, vp, i64, ctypes.POINTER(i64)]),
+        "bfs_expand_bottom_up": (i32, [vp, ctypes.POINTER(vp)]),
         "bfs_merge_lists": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), i32,
                                   ctypes.POINTER(vp), i32, i32, ctypes.POINTER(i64),
                                   ctypes.POINTER(i64)]),
@@ -130,7 +131,7 @@ EXPORTED = ("bfs_options_default", "bfs_workspace_size", "bfs_plan_create", "bfs
             "bfs_last_error", "bfs_run", "bfs_begin", "bfs_expand", "bfs_merge_frontier",
             "bfs_finish", "bfs_level_stats", "bfs_plan_tuning", "bfs_batch_submit",
             "bfs_batch_wait", "bfs_batch_times", "bfs_batch_poll", "bfs_batch_tuning",
-            "bfs_frontier_list", "bfs_merge_lists")
+            "bfs_frontier_list", "bfs_merge_lists", "bfs_expand_bottom_up")
 
 
 class BfsError(RuntimeError):
@@ -298,6 +299,13 @@ class Plan:
         node's next-frontier bitmap."""
         p = ctypes.c_void_p(0)
         self._check(lib().bfs_expand(self.h, ctypes.byref(p)))
+        return int(p.value or 0)
+
+    def expand_bottom_up(self) -> int:
+        """Phase 1 of the current level as a bottom-up step; returns the
+        device address of the node's next-frontier bitmap."""
+        p = ctypes.c_void_p(0)
+        self._check(lib().bfs_expand_bottom_up(self.h, ctypes.byref(p)))
         return int(p.value or 0)
 
     def merge_frontier(self, incoming=(), keep_next: bool = False):

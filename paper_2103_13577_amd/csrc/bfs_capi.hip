@@ -83,7 +83,7 @@ View bfs_plan_s::view(int32_t gi, int32_t *dist) const {
   v.dist = dist;
   v.visited = (uint64_t *)(b + lay.visited);
   v.next = (uint64_t *)(b + lay.next);
-  v.front = cur_do ? (uint64_t *)(b + lay.front) : nullptr;
+  v.front = cur_front ? (uint64_t *)(b + lay.front) : nullptr;
   for (int p = 0; p < kRing; ++p) {
     v.q0[p] = (int32_t *)(b + lay.q[0][p]);
     v.q1[p] = (int32_t *)(b + lay.q[1][p]);
@@ -281,6 +281,9 @@ bfs_status begin_impl(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist
   p->cur_dist = dist;
   p->cur_relabel = relabel;
   p->cur_do = relabel && p->direction_optimizing(graph);
+  // step-wise traversals of a plan created with BFS_DIR_OPTIMIZING keep the
+  // frontier bitmap for bfs_expand_bottom_up (any share)
+  p->cur_front = p->cur_do || (!relabel && p->opt.direction == BFS_DIR_OPTIMIZING);
   p->bu_state = false;
   p->front_level = -1;
   p->edges_after.clear();
@@ -325,6 +328,36 @@ bfs_status bfs_expand(bfs_plan_t p, const uint64_t **local_next) {
   if (e != hipSuccess) return p->hip_fail(e, "expand launch");
   if (timed) (void)hipEventRecord(p->lev[p->level][1], p->stream);
   p->expanded_level = p->level;
+  if (local_next) *local_next = v.next;
+  return BFS_OK;
+}
+
+bfs_status bfs_expand_bottom_up(bfs_plan_t p, const uint64_t **local_next) {
+  if (!p) return BFS_ERR_ARG;
+  if (!p->began || p->finished) return p->fail(BFS_ERR_STATE, "bfs_expand_bottom_up before bfs_begin");
+  if (p->expanded_level == p->level) return p->fail(BFS_ERR_STATE, "level already expanded");
+  if (p->cur_relabel || !p->cur_front)
+    return p->fail(BFS_ERR_STATE, "bottom-up steps need a traversal started by bfs_begin on a plan "
+                                  "created with direction = BFS_DIR_OPTIMIZING");
+  if (p->level > 0 && p->front_level != p->level)
+    return p->fail(BFS_ERR_STATE, "the previous level was not finished by a merge");
+  View v = p->view(p->cur_graph, p->cur_dist);
+  if (p->opt.collect_stats && p->level + 1 < kMaxStatLevels) {
+    hipError_t e = launch_clear_stats_row(v, p->level + 1, p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "stats launch");
+  }
+  const bool timed = p->time_levels && p->level < Plan::kTimedLevels;
+  if (timed) {
+    p->level_kind[p->level] = 2;
+    (void)hipEventRecord(p->lev[p->level][0], p->stream);
+  }
+  // level 0: the frontier is the root alone, which is what `visited` holds
+  const uint64_t *front = p->level == 0 ? v.visited : v.front;
+  hipError_t e = launch_bottom_up(v, p->level, p->num_cus * std::max(p->bpc_bu, 1), 0u, front, p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "bottom-up launch");
+  if (timed) (void)hipEventRecord(p->lev[p->level][1], p->stream);
+  p->expanded_level = p->level;
+  p->bu_levels_run += 1;
   if (local_next) *local_next = v.next;
   return BFS_OK;
 }
@@ -481,7 +514,7 @@ bfs_status bottom_up_level(bfs_plan_t p, int64_t *global_new) {
   if (p->front_level != p->level) e = launch_front_from_queues(v, p->level, p->wide_grid(), p->stream);
   const uint32_t hot = (uint32_t)std::min<int64_t>(kBottomUpHot, v.words);
   if (e == hipSuccess)
-    e = launch_bottom_up(v, p->level, p->num_cus * std::max(p->bpc_bu, 1), hot, p->stream);
+    e = launch_bottom_up(v, p->level, p->num_cus * std::max(p->bpc_bu, 1), hot, v.front, p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "bottom-up launch");
   if (timed) (void)hipEventRecord(p->lev[p->level][1], p->stream);
   p->expanded_level = p->level;

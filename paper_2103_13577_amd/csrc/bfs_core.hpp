@@ -60,7 +60,8 @@ struct View {
   uint64_t *visited;
   uint64_t *next;
   uint64_t *front;        // direction-optimizing traversal: frontier bitmap of the
-                          // next level, written by every dense merge (NULL: off)
+                          // next level (the level's merged global queue), written
+                          // by every merge that finishes a level (NULL: off)
   int32_t *q0[kRing];
   int32_t *q1[kRing];
   int32_t *q2[kRing];
@@ -112,7 +113,8 @@ hipError_t enqueue_graph_levels(const View &v, int levels, int max_levels, int e
                                 int merge_grid, uint32_t hot_words, hipStream_t s);
 int persistent_blocks_per_cu(int variant);
 int expand_blocks_per_cu(uint32_t hot_words);
-hipError_t launch_bottom_up(const View &v, int level, int grid, uint32_t hot_words, hipStream_t s);
+hipError_t launch_bottom_up(const View &v, int level, int grid, uint32_t hot_words, const uint64_t *front,
+                            hipStream_t s);
 hipError_t launch_front_from_queues(const View &v, int level, int grid, hipStream_t s);
 int bottom_up_blocks_per_cu(uint32_t hot_words);
 size_t cu_lds_bytes(int64_t words);

@@ -495,8 +495,12 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
       } else if (nx) {
         v.next[w] = 0ull;
       }
-      if (w == v.words - 1 && (v.n & 63)) nw &= ~0ull >> (64 - (v.n & 63));
-      if (v.front && !a.keep_next) v.front[w] = nw;  // the next level's frontier bitmap
+      const uint64_t tail = (w == v.words - 1 && (v.n & 63)) ? ~0ull >> (64 - (v.n & 63)) : ~0ull;
+      nw &= tail;
+      // the next level's frontier bitmap: the level's whole global queue
+      // (every vertex found in the level, also those merged by earlier
+      // keep_next calls of a multi-round exchange)
+      if (v.front && !a.keep_next) v.front[w] = m & tail;
       om = nw & owned_mask(w, v.vb, v.ve);
     }
     my_new += (uint64_t)__popcll(nw);
@@ -734,15 +738,18 @@ __global__ void __launch_bounds__(kBlock) k_merge(View v, MergeArgs a) {
 
 constexpr int kBuUnroll = 4;  // adjacency entries per lane in flight
 
-// Level L bottom-up: one wavefront per 64-vertex word of `visited`, one lane
-// per unvisited vertex. A lane scans its vertex's adjacency kBuUnroll entries
-// at a time until a neighbour is set in the level-L frontier bitmap; the
-// vertices found in a word go to `next` with one store (each word belongs to
-// one wavefront), and the ordinary merge then finishes the level (distances,
-// visited, queues and the next frontier bitmap). The first frontier words are
-// copied to LDS: on a relabelled graph every adjacency list starts with the
-// hubs, so the first probes of most lanes are LDS reads.
-__global__ void __launch_bounds__(kBlock) k_bottom_up(View v, int level, uint32_t hot_words) {
+// Level L bottom-up: one wavefront per 64-vertex word of `visited` within
+// the owned range, one lane per unvisited owned vertex. A lane scans its
+// vertex's adjacency kBuUnroll entries at a time until a neighbour is set in
+// `front`, the level-L frontier bitmap over all n vertices (on a share it is
+// the merged result of the previous level's exchange); the vertices found in
+// a word go to `next` with one store (each word belongs to one wavefront),
+// and the ordinary merge then finishes the level (distances, visited, queues
+// and the next frontier bitmap). The first frontier words are copied to LDS:
+// on a relabelled graph every adjacency list starts with the hubs, so the
+// first probes of most lanes are LDS reads.
+__global__ void __launch_bounds__(kBlock) k_bottom_up(View v, int level, uint32_t hot_words,
+                                                      const uint64_t *front) {
   extern __shared__ uint64_t s_hot[];
   __shared__ uint64_t s_acc[2][kWavesPerBlock];
   const int lane = lane_id();
@@ -758,18 +765,19 @@ __global__ void __launch_bounds__(kBlock) k_bottom_up(View v, int level, uint32_
     v.ctl->ownedcnt[(level + 1) % 3] = 0;
   }
   const uint32_t hw = (uint32_t)min<int64_t>(hot_words, v.words);
-  for (uint32_t i = threadIdx.x; i < hw; i += kBlock) s_hot[i] = v.front[i];
+  for (uint32_t i = threadIdx.x; i < hw; i += kBlock) s_hot[i] = front[i];
   __syncthreads();
   uint64_t examined = 0, verts = 0;
-  for (uint64_t w = gwave; w < (uint64_t)v.words; w += nwaves) {
+  const uint64_t wb = (uint64_t)(v.vb >> 6), we = (uint64_t)((v.ve + 63) >> 6);
+  for (uint64_t w = wb + gwave; w < we; w += nwaves) {
     const uint64_t vis = v.visited[w];
     if (vis == ~0ull) continue;
     const int64_t x = (int64_t)w * 64 + lane;
-    bool todo = x < v.n && !((vis >> lane) & 1ull);
+    bool todo = x >= v.vb && x < v.ve && !((vis >> lane) & 1ull);
     int64_t k = 0, e = 0;
     if (todo) {
-      k = v.rp[x];
-      e = v.rp[x + 1];
+      k = v.rp[x - v.vb];
+      e = v.rp[x - v.vb + 1];
       todo = k < e;
     }
     const int64_t k0 = k;
@@ -786,7 +794,7 @@ __global__ void __launch_bounds__(kBlock) k_bottom_up(View v, int level, uint32_
             // address-space-qualified reads stay LDS and global instructions
             uint64_t fw;
             if (uw < hw) fw = s_hot[uw];
-            else fw = ((const __attribute__((address_space(1))) uint64_t *)v.front)[uw];
+            else fw = ((const __attribute__((address_space(1))) uint64_t *)front)[uw];
             if ((fw >> (u[j] & 63)) & 1ull) found = true;
           }
         }
@@ -1061,8 +1069,10 @@ hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, 
   return hipGetLastError();
 }
 
-hipError_t launch_bottom_up(const View &v, int level, int grid, uint32_t hot_words, hipStream_t s) {
-  hipLaunchKernelGGL(k_bottom_up, dim3(grid), dim3(kBlock), (size_t)hot_words * 8, s, v, level, hot_words);
+hipError_t launch_bottom_up(const View &v, int level, int grid, uint32_t hot_words, const uint64_t *front,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_bottom_up, dim3(grid), dim3(kBlock), (size_t)hot_words * 8, s, v, level, hot_words,
+                     front);
   return hipGetLastError();
 }
 

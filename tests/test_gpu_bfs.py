@@ -396,6 +396,111 @@ def test_list_export_many_blocks(gpu):
     plan.close()
 
 
+def _bottom_up_level(pattern, L, frontier, n):
+    if pattern == "all":
+        return True
+    if pattern == "alternate":
+        return L % 2 == 1
+    return frontier * 24 >= n  # "rule": large frontiers go bottom-up
+
+
+@pytest.mark.parametrize("scale,P,radix,node,pattern,rounds", [
+    (14, 16, 2, 0, "rule", False), (14, 16, 4, 5, "alternate", True), (13, 16, 2, 7, "all", True),
+    (12, 4, 2, 3, "alternate", False), (14, 1, 2, 0, "rule", False), (13, 2, 2, 1, "all", False)])
+def test_partition_share_bottom_up(gpu, scale, P, radix, node, pattern, rounds):
+    """Bottom-up Phase 1 steps on a share behind the staged butterfly
+    exchange: after a bottom-up step the node's local bitmap equals its owned
+    vertices of the next level (oracle bottom-up staging), after a top-down
+    step the oracle's top-down set; merged at once or one round at a time, the
+    traversal gives the oracle's counts, distances and owned parents."""
+    import torch
+    g = gg.rmat(scale, 8, seed=100 + scale, perm_seed=200 + scale)
+    src = int(gg.pick_sources(g, 1, seed=300 + scale)[0])
+    ref = oracle.bfs(g, src)
+    b = gg.partition_1d(g.row_ptr, P)
+    lo, hi = int(b[node]), int(b[node + 1])
+    td = oracle.stage(g, ref, b, node, radix)
+    bu = oracle.stage_bottom_up(g.n, ref, b, node, radix)
+    nlev = td[0].shape[0]
+    W = (g.n + 63) // 64
+    zeros = np.zeros(W, dtype=np.uint64)
+    dg = pkg.DeviceGraph.from_csr(g, gpu, lo, hi)
+    plan = pkg.Plan([dg], direction=pkg.DIR_OPTIMIZING)
+    dist = torch.empty(g.n, dtype=torch.int32, device=gpu)
+    parent = torch.empty(g.n, dtype=torch.int32, device=gpu)
+    plan.begin(0, src, dist)
+    L, n_bu = 0, 0
+    frontier = 1
+    while True:
+        up = _bottom_up_level(pattern, L, frontier, g.n)
+        n_bu += int(up)
+        local, inc = bu if up else td
+        addr = plan.expand_bottom_up() if up else plan.expand()
+        exp = local[L] if L < nlev else zeros
+        assert np.array_equal(_read_device_words(addr, W, gpu), exp), (L, up)
+        msgs = [_words_to_tensor(inc[L, j] if L < nlev else zeros, gpu) for j in range(inc.shape[1])]
+        if rounds and len(msgs) > 1:
+            per = radix - 1
+            for r0 in range(0, len(msgs), per):
+                gnew, onew = plan.merge_frontier(msgs[r0:r0 + per], keep_next=r0 + per < len(msgs))
+        else:
+            gnew, onew = plan.merge_frontier(msgs)
+        assert gnew == int((ref == L + 1).sum())
+        assert onew == int((ref == L + 1)[lo:hi].sum())
+        frontier = gnew
+        if gnew == 0:
+            break
+        L += 1
+    st = plan.finish(parent)
+    assert st.levels == L + 1 == ref.max() + 1
+    assert st.bottom_up_levels == n_bu
+    assert np.array_equal(dist.cpu().numpy(), ref)
+    assert np.array_equal(parent.cpu().numpy()[lo:hi], oracle.parent(g, ref)[lo:hi])
+    plan.close()
+
+
+def test_bottom_up_step_errors(gpu):
+    """A plan without BFS_DIR_OPTIMIZING, a second expansion of one level and
+    a bottom-up step before bfs_begin are refused; bfs_run's traversal of the
+    relabelled copy is not a step-wise one."""
+    import torch
+    g = gg.rmat(11, 8, seed=91, perm_seed=92)
+    src = int(gg.pick_sources(g, 1, seed=93)[0])
+    dist = torch.empty(g.n, dtype=torch.int32, device=gpu)
+    plain = pkg.Plan([pkg.DeviceGraph.from_csr(g, gpu)], autotune=-1)
+    plain.begin(0, src, dist)
+    with pytest.raises(pkg.BfsError) as e:
+        plain.expand_bottom_up()
+    assert e.value.status == 7
+    plain.close()
+    plan = pkg.Plan([pkg.DeviceGraph.from_csr(g, gpu)], autotune=-1, direction=pkg.DIR_OPTIMIZING)
+    with pytest.raises(pkg.BfsError) as e:
+        plan.expand_bottom_up()
+    assert e.value.status == 7
+    plan.begin(0, src, dist)
+    plan.expand_bottom_up()
+    with pytest.raises(pkg.BfsError) as e:
+        plan.expand_bottom_up()
+    assert e.value.status == 7
+    with pytest.raises(pkg.BfsError) as e:
+        plan.expand()
+    assert e.value.status == 7
+    plan.merge_frontier([])
+    while True:
+        plan.expand_bottom_up()
+        gnew, _ = plan.merge_frontier([])
+        if gnew == 0:
+            break
+    plan.finish()
+    assert np.array_equal(dist.cpu().numpy(), ref := oracle.bfs(g, src))
+    d, _, st = plan.run(0, src)
+    assert np.array_equal(d.cpu().numpy(), ref)
+    with pytest.raises(pkg.BfsError) as e:
+        plan.expand_bottom_up()
+    assert e.value.status == 7
+    plan.close()
+
+
 def _read_device_words(addr, W, gpu):
     """Copies W uint64 words at a raw device address to the host (hipMemcpy)."""
     import torch

@@ -421,3 +421,53 @@ def test_stage_lists_match_algorithm2_queues(radix):
         flat = [s for rnd in r["rounds"] for s in rnd]
         for j, s in enumerate(flat):
             assert oracle.bitmap_list(inc[L, j], g.n).tolist() == sorted(s)
+
+
+# ---------------------------------------------------------------------------
+# bottom-up Phase 1 behind the butterfly exchange
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("radix,P,node,bu", [(2, 16, 0, "all"), (4, 16, 5, "all"), (2, 8, 3, "mixed"),
+                                             (4, 16, 0, "mixed")])
+def test_stage_bottom_up_matches_algorithm2_simulation(radix, P, node, bu):
+    """Algorithm 2 simulated with bottom-up Phase 1 steps on some levels ends
+    with the plain BFS distances on every node, and every level's local set
+    and received queues equal the bottom-up staging on bottom-up levels and
+    the top-down staging elsewhere."""
+    g = gg.rmat(10, 8, seed=70 + P, perm_seed=71)
+    src = int(gg.pick_sources(g, 1, seed=72)[0])
+    d = oracle.bfs(g, src)
+    b = gg.partition_1d(g.row_ptr, P)
+    nlev = int(d.max())
+    levels = set(range(nlev + 1)) if bu == "all" else {1, 3}
+    dl, rec = bs.simulate(g, src, b, radix, node, bottom_up_levels=levels)
+    for c in range(P):
+        assert np.array_equal(dl[c], d)
+    td_local, td_inc = oracle.stage(g, d, b, node, radix)
+    bu_local, bu_inc = oracle.stage_bottom_up(g.n, d, b, node, radix)
+    assert len(rec) == nlev
+    for L, r in enumerate(rec):
+        local, inc = (bu_local, bu_inc) if L in levels else (td_local, td_inc)
+        assert r["local"] == _set(local[L]), L
+        flat = [s for rnd in r["rounds"] for s in rnd]
+        for j, s in enumerate(flat):
+            assert s == _set(inc[L, j]), (L, j)
+
+
+def test_stage_bottom_up_closed_form():
+    """Bottom-up messages hold only owned vertices of the next level: the
+    local set is the node's range of level L+1, and local plus the incoming
+    messages covers level L+1 exactly once per owner."""
+    g = gg.rmat(11, 8, seed=80, perm_seed=81)
+    src = int(gg.pick_sources(g, 1, seed=82)[0])
+    d = oracle.bfs(g, src)
+    b = gg.partition_1d(g.row_ptr, 16)
+    for node in (0, 9):
+        local, inc = oracle.stage_bottom_up(g.n, d, b, node, 2)
+        lo, hi = int(b[node]), int(b[node + 1])
+        for L in range(local.shape[0]):
+            lev = set(np.flatnonzero(d == L + 1).tolist())
+            assert _set(local[L]) == {v for v in lev if lo <= v < hi}
+            parts = [_set(local[L])] + [_set(inc[L, j]) for j in range(inc.shape[1])]
+            assert sum(len(x) for x in parts) == len(lev)  # disjoint
+            assert set().union(*parts) == lev
