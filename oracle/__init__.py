@@ -164,7 +164,8 @@ def bitmap_list(bm: np.ndarray, n: int) -> np.ndarray:
     return np.asarray(ids, dtype=np.int32)
 
 
-def stage_bottom_up(n: int, dist: np.ndarray, bounds: np.ndarray, node: int = 0, radix: int = 2):
+def stage_bottom_up(n: int, dist: np.ndarray, bounds: np.ndarray, node: int = 0, radix: int = 2,
+                    levels=None):
     """Butterfly inputs for compute node ``node`` when Phase 1 of every level
     is a bottom-up step, in the layout of :func:`stage`.
 
@@ -172,7 +173,8 @@ def stage_bottom_up(n: int, dist: np.ndarray, bounds: np.ndarray, node: int = 0,
     neighbour in the level-L frontier, which is every owned vertex at distance
     L+1, so X_c(L) = {u owned by c : d[u] = L+1}. In round i the partner that
     differs from ``node`` in base-radix digit i sends the union of X_c over its
-    aligned block of radix^i nodes (the queues it has merged so far).
+    aligned block of radix^i nodes (the queues it has merged so far). With
+    ``levels`` given, only those levels are filled (the others stay empty).
     """
     P = len(bounds) - 1
     depth, pw = 0, 1
@@ -184,19 +186,22 @@ def stage_bottom_up(n: int, dist: np.ndarray, bounds: np.ndarray, node: int = 0,
     K = depth * (radix - 1)
     nlev = int(max(int(dist.max()), 0))
     W = (n + 63) // 64
-    owner = np.searchsorted(np.asarray(bounds, dtype=np.int64), np.arange(n), side="right") - 1
+    bounds = np.asarray(bounds, dtype=np.int64)
 
-    def bitmap(mask):
-        bm = np.zeros(W, dtype=np.uint64)
-        ids = np.flatnonzero(mask).astype(np.uint64)
-        np.bitwise_or.at(bm, (ids >> np.uint64(6)).astype(np.int64), np.uint64(1) << (ids & np.uint64(63)))
-        return bm
+    def bitmap(lev, first_node, count):
+        # bit v (v in the nodes' ranges) = lev[v]; bit v is bit v & 63 of word v >> 6
+        a, b = int(bounds[first_node]), int(bounds[first_node + count])
+        sel = np.zeros(W * 64, dtype=bool)
+        sel[a:b] = lev[a:b]
+        return np.packbits(sel, bitorder="little").view("<u8").astype(np.uint64)
 
     local = np.zeros((nlev, W), dtype=np.uint64)
     inc = np.zeros((nlev, K, W), dtype=np.uint64)
     for L in range(nlev):
+        if levels is not None and L not in levels:
+            continue
         lev = dist == L + 1
-        local[L] = bitmap(lev & (owner == node))
+        local[L] = bitmap(lev, node, 1)
         k = 0
         for i in range(depth):
             step = radix ** i
@@ -206,7 +211,7 @@ def stage_bottom_up(n: int, dist: np.ndarray, bounds: np.ndarray, node: int = 0,
                     continue
                 partner = node + (j - digit) * step
                 lo = (partner // step) * step  # the partner's block of radix^i nodes
-                inc[L, k] = bitmap(lev & (owner >= lo) & (owner < lo + step))
+                inc[L, k] = bitmap(lev, lo, step)
                 k += 1
     return local, inc
 
