@@ -509,8 +509,8 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
     if (!__syncthreads_or(nw != 0ull)) continue;
 
     // Pass 1: distances of new vertices; degree tier of owned new vertices.
-    // Words are taken four at a time (lanes = the 64 bits of a word) so the
-    // row-offset loads of four words are in flight together.
+    // Words are taken eight at a time (lanes = the 64 bits of a word) so the
+    // row-offset loads of eight words are in flight together.
     uint64_t t1m = 0, t2m = 0;
     uint64_t chunks = 0;  // wave-uniform
     uint64_t act = ballot(nw != 0);
@@ -528,7 +528,7 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
       }
     }
     while (act) {
-      constexpr int kW = 4;
+      constexpr int kW = 8;
       int js[kW];
       int cnt = 0;
 #pragma unroll
