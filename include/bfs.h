@@ -85,7 +85,7 @@ typedef int32_t (*bfs_exchange_fn)(void *ctx, int32_t level, const uint64_t *loc
 #define BFS_LOOP_PERSISTENT 2 /* whole traversal in one cooperative launch */
 #define BFS_LOOP_GRAPH 3      /* a captured hipGraph of 8 level steps, replayed until done */
 #define BFS_LOOP_CU 4         /* whole traversal in one workgroup with its bitmaps in LDS: whole
-                                 graphs with m < 2^25 whose three n-bit bitmaps fit in one
+                                 graphs with m < 2^25 whose two n-bit bitmaps fit in one
                                  workgroup's LDS (else BFS_ERR_ARG when asked for explicitly) */
 
 typedef struct {

@@ -635,7 +635,7 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
                                       p->max_lds)) {
     if (p->opt.loop_mode == BFS_LOOP_CU)
       return p->fail(BFS_ERR_ARG, "one-workgroup loop needs a whole graph with m < 2^25 whose "
-                                  "three bitmaps fit in one workgroup's LDS");
+                                  "two bitmaps fit in one workgroup's LDS");
     mode = BFS_LOOP_HOST;
   }
   const bool host_loop = mode == BFS_LOOP_HOST;

@@ -1,20 +1,23 @@
 // Whole traversal of a small graph by one workgroup, its bitmaps in LDS.
 //
-// For graphs whose visited, frontier and next bitmaps fit in one workgroup's
-// LDS (n up to a few hundred thousand vertices on gfx950), a traversal is
-// bound by per-level latency, not by bandwidth: the grid barriers of a
-// cooperative launch (each one a device-scope release and acquire on every
-// block) or a launch per phase cost more than the level's work. Here one
-// 1024-thread workgroup runs the same level-synchronous top-down steps
-// (Algorithm 1; Algorithm 2 with a single compute node) with workgroup
-// barriers between phases:
-//   expand - each wavefront takes frontier words; the set bits' adjacency
-//            lists are dealt evenly over the 64 lanes (a wavefront prefix sum
-//            and a binary search over the shuffled prefix values), and every
+// For graphs whose visited and next bitmaps fit in one workgroup's LDS (n up
+// to about half a million vertices on gfx950), a traversal is bound by
+// per-level latency, not by bandwidth: the grid barriers of a cooperative
+// launch (each one a device-scope release and acquire on every block) or a
+// launch per phase cost more than the level's work. Here one 1024-thread
+// workgroup runs the same level-synchronous top-down steps (Algorithm 1;
+// Algorithm 2 with a single compute node) with workgroup barriers between
+// phases:
+//   expand - the frontier queue is dealt 64 entries per wavefront, entry i to
+//            wavefront i mod 16 (so the hubs at the front of a degree-sorted
+//            queue spread over the wavefronts); each wavefront's 64 adjacency
+//            lists are dealt evenly over its lanes (a wavefront prefix sum and
+//            a binary search over the shuffled prefix values), and every
 //            neighbour whose visited bit is clear is ORed into the LDS next
 //            bitmap;
 //   merge  - new = next & ~visited per word; the new vertices get distance
-//            level+1 and become the frontier.
+//            level+1 and are appended to the next frontier queue (global
+//            memory, one LDS counter).
 // The control block receives the level count, the reached count and the
 // edges scanned, as the other level loops leave them.
 
@@ -35,26 +38,26 @@ __device__ __forceinline__ void lds_or(uint64_t *p, uint64_t bit) {
 }
 
 // Requires a whole graph (owned range [0, n)) with m < 2^25 edges, so one
-// wavefront's edge prefix sums fit in 32 bits, and 3 * words * 8 bytes of
-// dynamic LDS. dist was reset by k_reset.
+// wavefront's edge prefix sums fit in 32 bits, 2 * words * 8 bytes of dynamic
+// LDS, and two queue buffers of n entries (q0[0], q0[1]). dist was reset by
+// k_reset.
 __global__ void __launch_bounds__(kCuBlock) k_bfs_cu(View v, int64_t src_caller, int max_levels) {
   extern __shared__ uint64_t lds[];
   const int64_t W = v.words;
-  uint64_t *vis = lds, *front = lds + W, *nxt = lds + 2 * W;
-  __shared__ uint32_t s_new[3];
+  uint64_t *vis = lds, *nxt = lds + W;
+  __shared__ uint32_t s_qn[2];
   __shared__ unsigned long long s_edges;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / kWave;
   const int64_t src = v.new_id ? (int64_t)v.new_id[src_caller] : src_caller;
   for (int64_t w = tid; w < W; w += kCuBlock) {
-    const uint64_t b = (w == (src >> 6)) ? (1ull << (src & 63)) : 0ull;
-    vis[w] = b;
-    front[w] = b;
+    vis[w] = (w == (src >> 6)) ? (1ull << (src & 63)) : 0ull;
     nxt[w] = 0ull;
   }
   if (tid == 0) {
-    s_new[0] = s_new[1] = s_new[2] = 0;
+    v.q0[0][0] = (int32_t)src;
+    s_qn[0] = 1;
     s_edges = 0;
   }
   __syncthreads();
@@ -63,18 +66,25 @@ __global__ void __launch_bounds__(kCuBlock) k_bfs_cu(View v, int64_t src_caller,
   uint32_t nn = 0;
   int L = 0;
   for (;; ++L) {
-    // s_new[(L+1)%3] was last read two workgroup barriers ago; histogram row
-    // L+2 is first written by the merge of level L+1
-    if (tid == 0) s_new[(L + 1) % 3] = 0;
+    const int cur = L & 1, nx = cur ^ 1;
+    const int32_t *q = v.q0[cur];
+    int32_t *qn = v.q0[nx];
+    // queue counts are read as wave-uniform values, so the loop's exit test is
+    // uniform and the compiler keeps every lane in every iteration
+    const int64_t nq = __builtin_amdgcn_readfirstlane(s_qn[cur]);
+    // the counter this level's merge fills was last read at the previous
+    // level's start; the merge is one barrier away
+    if (tid == 0) s_qn[nx] = 0;
+    // histogram row L+2 is first written by the merge of level L+1
     if (v.stats && L + 2 < kMaxStatLevels && tid < kNumBins) v.lvl_hist[(L + 2) * kNumBins + tid] = 0;
-    // expand
-    for (int64_t w = wave; w < W; w += kCuWaves) {
-      const uint64_t f = front[w];
-      if (f == 0ull) continue;
-      const int64_t x = w * 64 + lane;
+    // expand: round r covers queue entries [r, r + 1024); lane l of wavefront
+    // w takes entry r + w + 16 l
+    for (int64_t r = 0; r < nq; r += kCuBlock) {
+      const int64_t i = r + wave + (int64_t)kCuWaves * lane;
       int64_t start = 0;
       int32_t deg = 0;
-      if ((f >> lane) & 1ull) {
+      if (i < nq) {
+        const int64_t x = q[i];
         start = v.rp[x];
         deg = (int32_t)(v.rp[x + 1] - start);
       }
@@ -107,30 +117,28 @@ __global__ void __launch_bounds__(kCuBlock) k_bfs_cu(View v, int64_t src_caller,
     }
     __syncthreads();
     // merge
-    uint32_t cnt = 0;
     for (int64_t w = wave; w < W; w += kCuWaves) {
       const uint64_t nw = nxt[w] & ~vis[w];
       if (nw != 0ull) {
+        uint32_t base = 0;
+        if (lane == 0) {
+          base = __hip_atomic_fetch_add(&s_qn[nx], (uint32_t)__popcll(nw), __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+          vis[w] |= nw;
+        }
+        base = __shfl(base, 0);
         if ((nw >> lane) & 1ull) {
           const int64_t x = w * 64 + lane;
           v.dist[v.old_id ? (int64_t)v.old_id[x] : x] = L + 1;
+          qn[base + rank_below(nw)] = (int32_t)x;
           if (v.stats && L + 1 < kMaxStatLevels)
             atomic_add32(&v.lvl_hist[(L + 1) * kNumBins + degree_bin(v.rp[x + 1] - v.rp[x])], 1u);
         }
-        if (lane == 0) {
-          vis[w] |= nw;
-          cnt += (uint32_t)__popcll(nw);
-        }
       }
-      if (lane == 0) {
-        front[w] = nw;
-        nxt[w] = 0ull;
-      }
+      if (lane == 0) nxt[w] = 0ull;
     }
-    if (lane == 0 && cnt)
-      (void)__hip_atomic_fetch_add(&s_new[L % 3], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __syncthreads();
-    nn = s_new[L % 3];
+    nn = __builtin_amdgcn_readfirstlane(s_qn[nx]);
     reached += nn;
     if (v.stats && tid == 0 && L + 1 < kMaxStatLevels) v.lvl_frontier[L + 1] = (int64_t)nn;
     if (nn == 0 || L + 1 >= max_levels) break;
@@ -151,7 +159,7 @@ __global__ void __launch_bounds__(kCuBlock) k_bfs_cu(View v, int64_t src_caller,
 }  // namespace
 
 // Dynamic LDS of the one-workgroup traversal of a graph with `words` bitmap words.
-size_t cu_lds_bytes(int64_t words) { return (size_t)words * 3 * sizeof(uint64_t); }
+size_t cu_lds_bytes(int64_t words) { return (size_t)words * 2 * sizeof(uint64_t); }
 
 // Whether the one-workgroup traversal can run graph g (whole graph, m below
 // 2^25, bitmaps within max_lds bytes of LDS next to the static LDS).

@@ -151,10 +151,11 @@ bfs_status choose_tuning(Plan *p) {
     const int64_t max_grid = std::min(per_cu * p->num_cus, kBarrierGroup * kBarrierMaxGroups);
     t.persist_grid = (int)std::max<int64_t>(1, std::min<int64_t>(max_grid, std::max<int64_t>(work_grid, 16)));
     t.loop_mode = (p->coop && per_cu > 0) ? BFS_LOOP_PERSISTENT : BFS_LOOP_HOST;
-    // small whole graphs: one workgroup with the bitmaps in LDS
+    // small whole graphs (up to 2^20 edges): one workgroup with the bitmaps
+    // in LDS
     const bfs_graph &gr = p->graphs[i];
     if (cu_fits(gr.n_global, m, gr.v_begin == 0 && gr.v_end == gr.n_global, p->max_lds) &&
-        !p->opt.exchange)
+        m <= (1ll << 20) && !p->opt.exchange)
       t.loop_mode = BFS_LOOP_CU;
     // cstart entries are 32-bit: total chunks must stay below 2^32.
     if ((m >> t.chunk_shift) + (p->graphs[i].v_end - p->graphs[i].v_begin) >= (1ll << 32))

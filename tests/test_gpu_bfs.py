@@ -396,6 +396,27 @@ def test_list_export_many_blocks(gpu):
     plan.close()
 
 
+@pytest.mark.parametrize("relabel", [0, -1])
+def test_cu_loop_larger_graphs(gpu, relabel):
+    """The one-workgroup loop on graphs that fill more of its LDS: R-MAT 16
+    (hubs) and a 500 x 400 grid with 2% of edges deleted (hundreds of levels,
+    so the two frontier queues alternate many times)."""
+    for g in (gg.rmat(16, 8, seed=611, perm_seed=612), gg.grid(500, 400, 0.02, seed=613)):
+        plan = pkg.Plan([pkg.DeviceGraph.from_csr(g, gpu)], loop_mode=pkg.LOOP_CU, relabel=relabel,
+                        autotune=-1)
+        for i, s in enumerate(gg.pick_sources(g, 3, seed=614)):
+            print(f"[gpu] cu loop n={g.n} src={s}", flush=True)
+            d, p, st = plan.run(0, int(s), parent=(i == 0))
+            ref = oracle.bfs(g, int(s))
+            assert np.array_equal(d.cpu().numpy(), ref)
+            if i == 0:
+                assert np.array_equal(p.cpu().numpy(), oracle.parent(g, ref))
+            assert st.levels == int(ref.max()) + 1
+            assert st.reached == int((ref >= 0).sum())
+            assert st.edges_scanned == oracle.edges_scanned(g, ref)
+        plan.close()
+
+
 def _bottom_up_level(pattern, L, frontier, n):
     if pattern == "all":
         return True
