@@ -194,7 +194,8 @@ typedef struct {
   int32_t wave_bin;
   int32_t chunk_edges;
   int32_t relabelled;       /* 1 if bfs_run traverses the degree-sorted copy */
-  float tuned_ms;           /* best traversal time seen by the autotuner (0: not tuned) */
+  float tuned_ms;           /* best mean traversal time the autotuner measured over its sources
+                               (0: not tuned) */
   int32_t hot_words;        /* visited words each expansion block keeps in LDS (0: none) */
   int32_t sparse_div;       /* single node: a level runs queue-only when its frontier is below
                                ceil(n/64) / sparse_div (0: never) */

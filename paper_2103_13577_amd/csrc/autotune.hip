@@ -1,5 +1,5 @@
-// Plan-time autotuner: times a few whole traversals per candidate setting on
-// the plan's own graph and keeps the fastest. Candidates: the level loop
+// Plan-time autotuner: times a few whole traversals from four sources per
+// candidate setting on the plan's own graph and keeps the fastest. Candidates: the level loop
 // (host-driven launches per phase, a captured graph of level steps, the
 // cooperative persistent loop with either register budget and several grid
 // sizes, or one workgroup for small graphs), the degree-bin thresholds that
@@ -27,47 +27,81 @@ bool tune_wanted(const Plan *p, size_t gi) {
   return true;
 }
 
-// A source with at least one edge, in caller ids: the highest-degree vertex
-// when the graph is relabelled, else the first vertex with an edge.
-bfs_status pick_source(Plan *p, size_t gi, int64_t &src) {
+// Sources with at least one edge, in caller ids, placed like typical
+// sources (a traversal's level profile depends on where it starts). On a
+// relabelled graph: the vertices at degree ranks z/8, z/4, z/2 and 3z/4, z the
+// number of vertices with an edge (found by bisection of the degree-sorted
+// row offsets). Else up to four vertices with an edge spread over the first
+// 2^16 ids.
+bfs_status pick_sources(Plan *p, size_t gi, std::vector<int64_t> &srcs) {
   const bfs_graph &g = p->graphs[gi];
-  src = 0;
+  srcs.clear();
+  char *w = (char *)p->ws;
   if (p->lay.rl_old[gi]) {
-    int32_t v = 0;
-    hipError_t e = hipMemcpy(&v, (char *)p->ws + p->lay.rl_old[gi], sizeof(int32_t),
-                             hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return p->hip_fail(e, "autotune source");
-    src = v;
+    const int64_t *rp = (const int64_t *)(w + p->lay.rl_rp[gi]);
+    const int32_t *old_id = (const int32_t *)(w + p->lay.rl_old[gi]);
+    auto has_edge = [&](int64_t k, bool &out) -> bfs_status {
+      int64_t r[2] = {0, 0};
+      hipError_t e = hipMemcpy(r, rp + k, sizeof(r), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return p->hip_fail(e, "autotune sources");
+      out = r[1] > r[0];
+      return BFS_OK;
+    };
+    int64_t lo = 0, hi = g.n_global;  // z = first rank without an edge, in [lo, hi]
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      bool he = false;
+      bfs_status st = has_edge(mid, he);
+      if (st) return st;
+      if (he) lo = mid + 1;
+      else hi = mid;
+    }
+    const int64_t z = std::max<int64_t>(lo, 1);
+    for (int64_t k : {z / 8, z / 4, z / 2, 3 * z / 4}) {
+      int32_t v = 0;
+      hipError_t e = hipMemcpy(&v, old_id + k, sizeof(int32_t), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return p->hip_fail(e, "autotune sources");
+      if (std::find(srcs.begin(), srcs.end(), (int64_t)v) == srcs.end()) srcs.push_back(v);
+    }
     return BFS_OK;
   }
   const int64_t cnt = std::min<int64_t>(g.n_global, 1 << 16);
   std::vector<int64_t> rp((size_t)cnt + 1);
   hipError_t e = hipMemcpy(rp.data(), g.row_ptr, sizeof(int64_t) * (cnt + 1), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return p->hip_fail(e, "autotune source");
-  for (int64_t v = 0; v < cnt; ++v)
-    if (rp[v + 1] > rp[v]) { src = v; break; }
+  if (e != hipSuccess) return p->hip_fail(e, "autotune sources");
+  for (int q = 0; q < 4; ++q)
+    for (int64_t v = q * cnt / 4; v < cnt; ++v)
+      if (rp[v + 1] > rp[v]) {
+        if (std::find(srcs.begin(), srcs.end(), v) == srcs.end()) srcs.push_back(v);
+        break;
+      }
+  if (srcs.empty()) srcs.push_back(0);
   return BFS_OK;
 }
 
-// Median of three timed traversals after one warm-up (the warm-up alone
-// when it is already three times slower than the best so far).
-bfs_status time_config(Plan *p, int32_t gi, int64_t src, float best, float &ms) {
+// Sum over the sources of the median of three timed traversals after one
+// warm-up (the first source's warm-up alone, scaled to all sources, when it
+// is already three times slower than the best so far).
+bfs_status time_config(Plan *p, int32_t gi, const std::vector<int64_t> &srcs, float best, float &ms) {
   int32_t *dist = (int32_t *)((char *)p->ws + p->lay.tune_dist);
   bfs_stats st;
-  bfs_status s = bfs_run(p, gi, src, dist, nullptr, &st);
-  if (s) return s;
-  if (st.ms > 3.f * best) {
-    ms = st.ms;
-    return BFS_OK;
-  }
-  float t[3];
-  for (float &x : t) {
-    s = bfs_run(p, gi, src, dist, nullptr, &st);
+  ms = 0.f;
+  for (size_t i = 0; i < srcs.size(); ++i) {
+    bfs_status s = bfs_run(p, gi, srcs[i], dist, nullptr, &st);
     if (s) return s;
-    x = st.ms;
+    if (i == 0 && st.ms * (float)srcs.size() > 3.f * best) {
+      ms = st.ms * (float)srcs.size();
+      return BFS_OK;
+    }
+    float t[3];
+    for (float &x : t) {
+      s = bfs_run(p, gi, srcs[i], dist, nullptr, &st);
+      if (s) return s;
+      x = st.ms;
+    }
+    std::sort(t, t + 3);
+    ms += t[1];
   }
-  std::sort(t, t + 3);
-  ms = t[1];
   return BFS_OK;
 }
 
@@ -76,8 +110,8 @@ bfs_status time_config(Plan *p, int32_t gi, int64_t src, float best, float &ms) 
 bfs_status autotune_graphs(Plan *p) {
   for (size_t gi = 0; gi < p->graphs.size(); ++gi) {
     if (!tune_wanted(p, gi) || !p->lay.tune_dist) continue;
-    int64_t src = 0;
-    bfs_status s = pick_source(p, gi, src);
+    std::vector<int64_t> src;
+    bfs_status s = pick_sources(p, gi, src);
     if (s) return s;
     Tuning &t = p->tune[gi];
     Tuning best = t;
@@ -102,6 +136,18 @@ bfs_status autotune_graphs(Plan *p) {
       loops.push_back(h);
       h.loop_mode = BFS_LOOP_GRAPH;
       loops.push_back(h);
+      // the per-phase loops run the large levels with an LDS hub copy on a
+      // relabelled graph, which the cooperative loop does not: compare them
+      // with one too, or the loop choice is made without their main advantage
+      int hw = 16384;
+      while (hw > 1024 && (int64_t)hw * 8 + 1024 > p->max_lds) hw /= 2;
+      if (p->lay.rl_rp[gi] && p->opt.hot_words == 0 && (int64_t)hw * 8 + 1024 <= p->max_lds) {
+        h.hot_words = hw;
+        h.loop_mode = BFS_LOOP_HOST;
+        loops.push_back(h);
+        h.loop_mode = BFS_LOOP_GRAPH;
+        loops.push_back(h);
+      }
     }
     if (p->coop && (p->opt.loop_mode == BFS_LOOP_AUTO || p->opt.loop_mode == BFS_LOOP_PERSISTENT)) {
       // grids: all co-resident blocks, half of them, one block per CU, one
@@ -143,7 +189,7 @@ bfs_status autotune_graphs(Plan *p) {
       if ((s = trial(c))) return s;
     t = best;
     if (best.loop_mode == BFS_LOOP_CU) {  // the tier settings do not apply
-      t.tuned_ms = best_ms;
+      t.tuned_ms = best_ms / (float)src.size();
       continue;
     }
     // 2. tier thresholds (degree bins), each kept only if it helps
@@ -189,7 +235,7 @@ bfs_status autotune_graphs(Plan *p) {
         if ((s = trial(c))) return s;
       }
     t = best;
-    t.tuned_ms = best_ms;
+    t.tuned_ms = best_ms / (float)src.size();
   }
   return BFS_OK;
 }

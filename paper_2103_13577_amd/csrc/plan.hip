@@ -157,6 +157,8 @@ bfs_status choose_tuning(Plan *p) {
     if (cu_fits(gr.n_global, m, gr.v_begin == 0 && gr.v_end == gr.n_global, p->max_lds) &&
         m <= (1ll << 20) && !p->opt.exchange)
       t.loop_mode = BFS_LOOP_CU;
+    // an explicit loop is the one every setting is tuned and reported for
+    if (p->opt.loop_mode != BFS_LOOP_AUTO) t.loop_mode = p->opt.loop_mode;
     // cstart entries are 32-bit: total chunks must stay below 2^32.
     if ((m >> t.chunk_shift) + (p->graphs[i].v_end - p->graphs[i].v_begin) >= (1ll << 32))
       return p->fail(BFS_ERR_ARG, "chunk_edges too small for this graph");
