@@ -9,6 +9,11 @@
  * global next-frontier bitmap (Phase 1) followed by a frontier-synchronisation
  * merge of that bitmap with the bitmaps received from other compute nodes
  * (Phase 2). With one compute node the merge has no incoming bitmaps.
+ * Opt-in extensions on the same kernels and buffers: bottom-up Phase 1 steps
+ * (direction-optimizing traversal, whole graphs in bfs_run or any share
+ * through bfs_expand_bottom_up), vertex-list butterfly messages
+ * (bfs_frontier_list, bfs_merge_lists), and batched multi-source queries with
+ * a continuous-batching scheduler (bfs_batch_*).
  *
  * Conventions used by every entry point
  *   - All graph, workspace, output and bitmap pointers are DEVICE pointers
@@ -104,10 +109,12 @@ typedef struct {
                               relabelled copy sorted by descending degree is built at plan
                               creation (inside the workspace); results keep original ids */
   int32_t autotune;        /* 0 = automatic (whole graphs with >= 2^16 edges), 1 = always,
-                              -1 = never. The plan times a few traversals per candidate
-                              (level loop, register budget, grid size, degree-bin tier
-                              thresholds) and keeps the fastest; explicit option values
-                              are never overridden */
+                              -1 = never. The plan times a few traversals from four sources
+                              per candidate (level loop, register budget, grid size,
+                              degree-bin tier thresholds, hub chunk size, LDS hub copy,
+                              queue-only threshold) and keeps the fastest; explicit option
+                              values are never overridden. Batched plans also tune the
+                              batched engine (bfs_batch_tuning) */
   int32_t hot_words;       /* relabelled graphs: visited words each expansion block keeps in
                               LDS on large levels; above 4096 words the expansion runs one
                               1024-thread block per CU sharing the copy. At most (LDS bytes
@@ -117,8 +124,9 @@ typedef struct {
                               frontier is below ceil(n/64) / sparse_div; 0 = tuned, -1 = never */
   int32_t direction;       /* BFS_DIR_TOPDOWN (default): every level top-down, the paper's
                               method. BFS_DIR_OPTIMIZING: bfs_run on a whole graph without an
-                              exchange callback may run large levels bottom-up (see below);
-                              ignored otherwise. Distances are the same either way */
+                              exchange callback may run large levels bottom-up (see below),
+                              and step-wise traversals may call bfs_expand_bottom_up.
+                              Distances are the same either way */
   int32_t reserved;
 } bfs_options;
 
