@@ -98,6 +98,7 @@ View bfs_plan_s::view(int32_t gi, int32_t *dist) const {
   v.chunk_shift = tune[gi].chunk_shift;
   v.stats = opt.collect_stats ? 1 : 0;
   v.sparse_div = tune[gi].sparse_div;
+  v.into_vis = cur_into_vis ? 1 : 0;
   return v;
 }
 
@@ -285,6 +286,7 @@ bfs_status begin_impl(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist
   // frontier bitmap for bfs_expand_bottom_up (any share)
   p->cur_front = p->cur_do || (!relabel && p->opt.direction == BFS_DIR_OPTIMIZING);
   p->bu_state = false;
+  p->cur_into_vis = false;
   p->front_level = -1;
   p->edges_after.clear();
   p->bu_levels_run = 0;
@@ -692,10 +694,21 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
     p->persistent_levels = c.levels;
     p->level = c.levels;
   } else {
+    const int64_t words = (g.n_global + 63) / 64;
+    if (!p->opt.exchange && !p->cur_do && tu.sparse_div == 0) {
+      // every level dense and merged without incoming bitmaps: the
+      // expansions OR straight into `visited` (one bitmap for their random
+      // probes instead of two), and `next` holds visited as of each level's
+      // start, from which the merge finds the new vertices
+      p->cur_into_vis = true;
+      const View v0 = p->view(graph, dist);
+      e = hipMemcpyAsync(v0.next, v0.visited, sizeof(uint64_t) * (size_t)words, hipMemcpyDeviceToDevice,
+                         p->stream);
+      if (e != hipSuccess) return p->hip_fail(e, "visited snapshot");
+    }
     e = hipEventRecord(p->ev[2], p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
     p->time_levels = true;
-    const int64_t words = (g.n_global + 63) / 64;
     for (;;) {
       if (p->cur_do && p->level >= 2) {
         // edge-count test: frontier edges against the unvisited vertices' edges

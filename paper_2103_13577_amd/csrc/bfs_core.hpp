@@ -75,7 +75,9 @@ struct View {
   int32_t stats;
   int32_t sparse_div;     // device loop: a level runs queue-only when the
                           // frontier is below words / sparse_div (0 = never)
-  int32_t pad;
+  int32_t into_vis;       // single-node host loop without queue-only or bottom-up
+                          // levels: dense expansions OR straight into `visited`
+                          // and `next` holds visited as of the level's start
 };
 
 constexpr int kMaxIncoming = 8;  // received bitmaps per merge launch

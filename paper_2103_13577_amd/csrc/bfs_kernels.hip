@@ -141,11 +141,18 @@ __device__ __forceinline__ void probe_batch(const View &v, const int32_t (&u)[K]
   bool need[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) need[j] = !((vis[j] >> (u[j] & 31)) & 1u);
+  // into_vis: the OR goes into `visited` itself; a target seen unvisited in
+  // global memory goes straight to the OR, one seen in the LDS snapshot is
+  // read again from global memory first
+  uint32_t *tgt32 = v.into_vis ? const_cast<uint32_t *>(vis32) : next32;
 #pragma unroll
-  for (int j = 0; j < K; ++j) nx[j] = need[j] ? next32[(uint32_t)u[j] >> 5] : ~0u;
+  for (int j = 0; j < K; ++j) {
+    nx[j] = ~0u;
+    if (need[j]) nx[j] = (v.into_vis && w[j] >= hot_w32) ? 0u : tgt32[(uint32_t)u[j] >> 5];
+  }
 #pragma unroll
   for (int j = 0; j < K; ++j)
-    if (!((nx[j] >> (u[j] & 31)) & 1u)) atomic_or_noret32(next32 + ((uint32_t)u[j] >> 5), 1u << (u[j] & 31));
+    if (!((nx[j] >> (u[j] & 31)) & 1u)) atomic_or_noret32(tgt32 + ((uint32_t)u[j] >> 5), 1u << (u[j] & 31));
 }
 
 // Dense probes of one adjacency range of `deg` entries starting at `row`
@@ -160,6 +167,7 @@ __device__ __forceinline__ void dense_rows(const View &v, const int32_t *row, in
   const int lane = lane_id();
   const uint32_t *vis32 = reinterpret_cast<const uint32_t *>(v.visited);
   uint32_t *next32 = reinterpret_cast<uint32_t *>(v.next);
+  uint32_t *tgt32 = v.into_vis ? reinterpret_cast<uint32_t *>(v.visited) : next32;
   const lds_u32 *hot32 = (const lds_u32 *)(hot.lds);
   const uint32_t hot_w32 = hot.words * 2;
   for (int32_t r0 = 0; r0 < deg; r0 += kWave * K) {
@@ -188,15 +196,16 @@ __device__ __forceinline__ void dense_rows(const View &v, const int32_t *row, in
       const uint32_t vis = w < hot_w32 ? lv[j] : gv[j];
       need[j] = r0 + j * kWave + lane < deg && !((vis >> (u[j] & 31)) & 1u);
     }
+    // into_vis: as in probe_batch
     uint32_t nx[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       nx[j] = ~0u;
-      if (need[j]) nx[j] = next32[(uint32_t)u[j] >> 5];
+      if (need[j]) nx[j] = (v.into_vis && ((uint32_t)u[j] >> 5) >= hot_w32) ? 0u : tgt32[(uint32_t)u[j] >> 5];
     }
 #pragma unroll
     for (int j = 0; j < K; ++j)
-      if (!((nx[j] >> (u[j] & 31)) & 1u)) atomic_or_noret32(next32 + ((uint32_t)u[j] >> 5), 1u << (u[j] & 31));
+      if (!((nx[j] >> (u[j] & 31)) & 1u)) atomic_or_noret32(tgt32 + ((uint32_t)u[j] >> 5), 1u << (u[j] & 31));
   }
 }
 
@@ -483,7 +492,14 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
     const int64_t wbase = g0 + wave * kWave;  // first word of this wavefront
     const int64_t w = wbase + lane;
     uint64_t nw = 0, om = 0;
-    if (w < v.words) {
+    if (w < v.words && v.into_vis) {
+      // the expansion ORed into `visited`; `next` holds visited as it was at
+      // the level's start, and becomes the current visited
+      const uint64_t vis = v.visited[w], prev = v.next[w];
+      nw = vis & ~prev;
+      if (nw) v.next[w] = vis;
+      om = nw & owned_mask(w, v.vb, v.ve);
+    } else if (w < v.words) {
       const uint64_t nx = v.next[w];
       uint64_t m = nx;
       for (int j = 0; j < a.k; ++j) m |= a.inc[j][w];

@@ -101,6 +101,7 @@ struct bfs_plan_s {
   // direction-optimizing traversal (bfs_run, whole graph, no exchange)
   bool cur_do = false;                // the running traversal may go bottom-up
   bool cur_front = false;             // merges write the next level's frontier bitmap
+  bool cur_into_vis = false;          // dense expansions OR into `visited` (see View::into_vis)
   bool bu_state = false;              // the current level runs bottom-up
   int front_level = -1;               // level whose frontier the front bitmap holds
   std::vector<int64_t> edges_after;   // edge counter (sum of reached degrees) after each level

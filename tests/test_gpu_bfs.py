@@ -64,7 +64,12 @@ MODES = [dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST),
          # direction-optimizing: large levels bottom-up (next row of the paper's outlook)
          dict(direction=pkg.DIR_OPTIMIZING),
          dict(direction=pkg.DIR_OPTIMIZING, sparse_div=-1, relabel=-1),
-         dict(loop_mode=pkg.LOOP_GRAPH, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64)]
+         dict(loop_mode=pkg.LOOP_GRAPH, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64),
+         # every level dense in the host-driven loop: the expansions OR into
+         # the visited bitmap itself (narrow and wide expansion, both tiers)
+         dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1, hot_words=16384, small_bin=3, wave_bin=6,
+              chunk_edges=128),
+         dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64)]
 
 
 @pytest.mark.parametrize("name,make,sources", SMALL_GRAPHS, ids=[x[0] for x in SMALL_GRAPHS])
