@@ -603,6 +603,24 @@ bfs_status graph_exec(bfs_plan_t p, int32_t gi, hipGraphExec_t &out) {
 
 }  // namespace
 
+namespace {
+
+// A traversal whose levels are all dense and merged without incoming bitmaps
+// (single node, no queue-only or bottom-up levels) lets its expansions OR
+// straight into `visited` (one bitmap for their random probes instead of two);
+// `next` then holds visited as of each level's start, from which the merge
+// finds the new vertices. Called after the reset, before the level loop.
+bfs_status into_visited(bfs_plan_t p, int32_t graph, int32_t *dist) {
+  if (p->opt.exchange || p->cur_do || p->tune[graph].sparse_div != 0) return BFS_OK;
+  p->cur_into_vis = true;
+  const View v = p->view(graph, dist);
+  hipError_t e = hipMemcpyAsync(v.next, v.visited, sizeof(uint64_t) * (size_t)v.words,
+                                hipMemcpyDeviceToDevice, p->stream);
+  return e == hipSuccess ? BFS_OK : p->hip_fail(e, "visited snapshot");
+}
+
+}  // namespace
+
 bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, int32_t *parent,
                    bfs_stats *st) {
   if (!p) return BFS_ERR_ARG;
@@ -657,6 +675,8 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
     p->persistent_levels = c.levels;
     p->level = c.levels;
   } else if (mode == BFS_LOOP_GRAPH) {
+    s = into_visited(p, graph, dist);  // before the capture, which keeps the setting
+    if (s) return s;
     hipGraphExec_t ge = nullptr;
     s = graph_exec(p, graph, ge);
     if (s) return s;
@@ -678,6 +698,8 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
     p->persistent_levels = c.levels;
     p->level = c.levels;
   } else if (!host_loop) {
+    s = into_visited(p, graph, dist);
+    if (s) return s;
     View v = p->view(graph, dist);
     const int max_levels = (int)std::min<int64_t>(g.n_global + 1, 1ll << 30);
     e = hipEventRecord(p->ev[2], p->stream);
@@ -695,17 +717,8 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
     p->level = c.levels;
   } else {
     const int64_t words = (g.n_global + 63) / 64;
-    if (!p->opt.exchange && !p->cur_do && tu.sparse_div == 0) {
-      // every level dense and merged without incoming bitmaps: the
-      // expansions OR straight into `visited` (one bitmap for their random
-      // probes instead of two), and `next` holds visited as of each level's
-      // start, from which the merge finds the new vertices
-      p->cur_into_vis = true;
-      const View v0 = p->view(graph, dist);
-      e = hipMemcpyAsync(v0.next, v0.visited, sizeof(uint64_t) * (size_t)words, hipMemcpyDeviceToDevice,
-                         p->stream);
-      if (e != hipSuccess) return p->hip_fail(e, "visited snapshot");
-    }
+    s = into_visited(p, graph, dist);
+    if (s) return s;
     e = hipEventRecord(p->ev[2], p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
     p->time_levels = true;

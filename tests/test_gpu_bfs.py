@@ -69,7 +69,9 @@ MODES = [dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST),
          # the visited bitmap itself (narrow and wide expansion, both tiers)
          dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1, hot_words=16384, small_bin=3, wave_bin=6,
               chunk_edges=128),
-         dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64)]
+         dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64),
+         dict(loop_mode=pkg.LOOP_GRAPH, sparse_div=-1, hot_words=16384),
+         dict(loop_mode=pkg.LOOP_PERSISTENT, sparse_div=-1, small_bin=2, wave_bin=4, chunk_edges=64)]
 
 
 @pytest.mark.parametrize("name,make,sources", SMALL_GRAPHS, ids=[x[0] for x in SMALL_GRAPHS])
