@@ -552,25 +552,36 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
         js[q] = act ? __ffsll((unsigned long long)act) - 1 : 0;
         if (act) { act &= act - 1; ++cnt; }
       }
-      bool own[kW];
-      int64_t r0[kW], r1[kW];
+      bool own[kW], isnew[kW];
+      int64_t vtx[kW], r0[kW], r1[kW];
 #pragma unroll
       for (int q = 0; q < kW; ++q) {
-        own[q] = false;
-        r0[q] = r1[q] = 0;
-        if (q < cnt) {
-          const uint64_t wj = readlane64(nw, js[q]);
-          const uint64_t oj = readlane64(om, js[q]);
-          const int64_t vtx = (wbase + js[q]) * 64 + lane;
-          if ((wj >> lane) & 1ull) dist[v.old_id ? (int64_t)v.old_id[vtx] : vtx] = dnew;
-          own[q] = (oj >> lane) & 1ull;
-          if (own[q]) {
-            const int64_t li = vtx - v.vb;
-            r0[q] = v.rp[li];
-            r1[q] = v.rp[li + 1];
-          }
-        }
+        const uint64_t wj = q < cnt ? readlane64(nw, js[q]) : 0ull;
+        const uint64_t oj = q < cnt ? readlane64(om, js[q]) : 0ull;
+        vtx[q] = (wbase + js[q]) * 64 + lane;
+        isnew[q] = (wj >> lane) & 1ull;
+        own[q] = (oj >> lane) & 1ull;
       }
+      // Every load of the batch is issued before the first store that
+      // depends on one: loads are unconditional, on addresses clamped into
+      // the arrays (this loop runs only when some word of the wavefront has
+      // an owned new vertex, so the owned range is not empty), so the
+      // wavefront waits for memory once per batch rather than once per word.
+      int32_t oid[kW];
+      if (v.old_id) {
+#pragma unroll
+        for (int q = 0; q < kW; ++q) oid[q] = v.old_id[min(vtx[q], v.n - 1)];
+      }
+      const int64_t nloc = v.ve - v.vb;
+#pragma unroll
+      for (int q = 0; q < kW; ++q) {
+        const int64_t li = min(max(vtx[q] - v.vb, (int64_t)0), nloc - 1);
+        r0[q] = v.rp[li];
+        r1[q] = v.rp[li + 1];
+      }
+#pragma unroll
+      for (int q = 0; q < kW; ++q)
+        if (isnew[q]) dist[v.old_id ? (int64_t)oid[q] : vtx[q]] = dnew;
 #pragma unroll
       for (int q = 0; q < kW; ++q) {
         if (q >= cnt) break;
