@@ -117,10 +117,13 @@ int bfs_plan_s::merge_grid(int64_t words) const {
 }
 
 bfs_status bfs_plan_s::read_ctl(Ctl &c) {
-  hipError_t e = hipMemcpyAsync(&c, (char *)ws + lay.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream);
+  // The host loop reads the control block after every level: the copy goes
+  // to pinned memory, which spares the staging copy of a pageable target.
+  hipError_t e = hipMemcpyAsync(hctl, (char *)ws + lay.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(ctl)");
   e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  c = *hctl;
   return BFS_OK;
 }
 
@@ -234,6 +237,12 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
       }
   if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     g_create_error = "hipStreamCreate failed";
+    delete p;
+    return BFS_ERR_HIP;
+  }
+  if (hipHostMalloc((void **)&p->hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+    p->hctl = nullptr;
+    g_create_error = "hipHostMalloc of the control block's host copy failed";
     delete p;
     return BFS_ERR_HIP;
   }

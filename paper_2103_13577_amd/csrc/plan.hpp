@@ -73,6 +73,7 @@ struct bfs_plan_s {
   int max_lds = 65536;          // dynamic LDS bytes one workgroup may use
   int expand_grid(int hot_words);
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bfsk::Ctl *hctl = nullptr;  // pinned host copy of the control block, read after each level
   static constexpr int kTimedLevels = 64;
   hipEvent_t lev[kTimedLevels][3] = {};  // per level: before expand, after expand, after merge
   bool time_levels = false;              // set while bfs_run drives the host loop
@@ -137,6 +138,7 @@ struct bfs_plan_s {
     for (auto &g : gexec)
       if (g) (void)hipGraphExecDestroy(g);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (hctl) (void)hipHostFree(hctl);
   }
 };
 
