@@ -74,11 +74,13 @@ View bfs_plan_s::view(int32_t gi, int32_t *dist) const {
     v.col = (const int32_t *)(b + lay.rl_col[gi]);
     v.old_id = (const int32_t *)(b + lay.rl_old[gi]);
     v.new_id = (const int32_t *)(b + lay.rl_new[gi]);
+    v.live_end = rl_live.size() > (size_t)gi ? rl_live[gi] : g.v_end;
   } else {
     v.rp = g.row_ptr;
     v.col = g.col;
     v.old_id = nullptr;
     v.new_id = nullptr;
+    v.live_end = g.v_end;
   }
   v.dist = dist;
   v.visited = (uint64_t *)(b + lay.visited);

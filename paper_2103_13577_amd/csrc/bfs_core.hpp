@@ -78,6 +78,8 @@ struct View {
   int32_t into_vis;       // single-node host loop without queue-only or bottom-up
                           // levels: dense expansions OR straight into `visited`
                           // and `next` holds visited as of the level's start
+  int64_t live_end;       // owned vertices at or above it have no edge (a
+                          // relabelled graph puts them last); else ve
 };
 
 constexpr int kMaxIncoming = 8;  // received bitmaps per merge launch

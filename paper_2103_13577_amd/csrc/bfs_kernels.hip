@@ -795,7 +795,9 @@ __global__ void __launch_bounds__(kBlock) k_bottom_up(View v, int level, uint32_
   for (uint32_t i = threadIdx.x; i < hw; i += kBlock) s_hot[i] = front[i];
   __syncthreads();
   uint64_t examined = 0, verts = 0;
-  const uint64_t wb = (uint64_t)(v.vb >> 6), we = (uint64_t)((v.ve + 63) >> 6);
+  // vertices without an edge are never found: a relabelled graph keeps them
+  // after live_end, and their words are skipped
+  const uint64_t wb = (uint64_t)(v.vb >> 6), we = (uint64_t)((min(v.ve, v.live_end) + 63) >> 6);
   for (uint64_t w = wb + gwave; w < we; w += nwaves) {
     const uint64_t vis = v.visited[w];
     if (vis == ~0ull) continue;

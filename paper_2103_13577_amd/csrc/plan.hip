@@ -116,6 +116,20 @@ bfs_status relabel_graphs(Plan *p) {
                                  p->lay.rl_temp_bytes, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "relabel");
+    // degrees descend with the new id: the first id without an edge, by
+    // bisection over the relabelled row offsets
+    const int64_t *rp = (const int64_t *)(w + p->lay.rl_rp[i]);
+    int64_t lo = 0, hi = g.n_global;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      int64_t r[2] = {0, 0};
+      e = hipMemcpy(r, rp + mid, sizeof(r), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return p->hip_fail(e, "relabel");
+      if (r[1] > r[0]) lo = mid + 1;
+      else hi = mid;
+    }
+    if (p->rl_live.size() < p->graphs.size()) p->rl_live.assign(p->graphs.size(), 0);
+    p->rl_live[i] = lo;
   }
   return BFS_OK;
 }

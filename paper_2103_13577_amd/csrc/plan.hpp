@@ -74,6 +74,7 @@ struct bfs_plan_s {
   int expand_grid(int hot_words);
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bfsk::Ctl *hctl = nullptr;  // pinned host copy of the control block, read after each level
+  std::vector<int64_t> rl_live;  // per relabelled graph: vertices with an edge (ids below it)
   static constexpr int kTimedLevels = 64;
   hipEvent_t lev[kTimedLevels][3] = {};  // per level: before expand, after expand, after merge
   bool time_levels = false;              // set while bfs_run drives the host loop
