@@ -30,33 +30,15 @@ bool tune_wanted(const Plan *p, size_t gi) {
 // Sources with at least one edge, in caller ids, placed like typical
 // sources (a traversal's level profile depends on where it starts). On a
 // relabelled graph: the vertices at degree ranks z/8, z/4, z/2 and 3z/4, z the
-// number of vertices with an edge (found by bisection of the degree-sorted
-// row offsets). Else up to four vertices with an edge spread over the first
-// 2^16 ids.
+// number of vertices with an edge (recorded when the graph was relabelled).
+// Else up to four vertices with an edge spread over the first 2^16 ids.
 bfs_status pick_sources(Plan *p, size_t gi, std::vector<int64_t> &srcs) {
   const bfs_graph &g = p->graphs[gi];
   srcs.clear();
   char *w = (char *)p->ws;
-  if (p->lay.rl_old[gi]) {
-    const int64_t *rp = (const int64_t *)(w + p->lay.rl_rp[gi]);
+  if (p->lay.rl_old[gi] && p->rl_live.size() > gi) {
     const int32_t *old_id = (const int32_t *)(w + p->lay.rl_old[gi]);
-    auto has_edge = [&](int64_t k, bool &out) -> bfs_status {
-      int64_t r[2] = {0, 0};
-      hipError_t e = hipMemcpy(r, rp + k, sizeof(r), hipMemcpyDeviceToHost);
-      if (e != hipSuccess) return p->hip_fail(e, "autotune sources");
-      out = r[1] > r[0];
-      return BFS_OK;
-    };
-    int64_t lo = 0, hi = g.n_global;  // z = first rank without an edge, in [lo, hi]
-    while (lo < hi) {
-      const int64_t mid = lo + (hi - lo) / 2;
-      bool he = false;
-      bfs_status st = has_edge(mid, he);
-      if (st) return st;
-      if (he) lo = mid + 1;
-      else hi = mid;
-    }
-    const int64_t z = std::max<int64_t>(lo, 1);
+    const int64_t z = std::max<int64_t>(p->rl_live[gi], 1);
     for (int64_t k : {z / 8, z / 4, z / 2, 3 * z / 4}) {
       int32_t v = 0;
       hipError_t e = hipMemcpy(&v, old_id + k, sizeof(int32_t), hipMemcpyDeviceToHost);
