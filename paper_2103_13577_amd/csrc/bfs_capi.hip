@@ -299,6 +299,8 @@ bfs_status begin_impl(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist
   p->bu_state = false;
   p->cur_into_vis = false;
   p->front_level = -1;
+  p->merge_mode = kMergeFull;
+  p->queues_stale = false;
   p->edges_after.clear();
   p->bu_levels_run = 0;
   p->level = 0;
@@ -321,6 +323,23 @@ bfs_status bfs_begin(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist)
   return begin_impl(p, graph, source, dist, false);
 }
 
+namespace {
+
+// Fills the current level's tier queues from the frontier bitmap after a
+// merge that left them unwritten.
+bfs_status fill_stale_queues(bfs_plan_t p, const View &v) {
+  if (!p->queues_stale) return BFS_OK;
+  MergeArgs a{};
+  a.level = p->level - 1;
+  a.mode = kMergeQueuesFromFront;
+  hipError_t e = launch_merge(v, a, p->merge_grid(v.words), p->stream);
+  if (e != hipSuccess) return p->hip_fail(e, "queue fill launch");
+  p->queues_stale = false;
+  return BFS_OK;
+}
+
+}  // namespace
+
 bfs_status bfs_expand(bfs_plan_t p, const uint64_t **local_next) {
   if (!p) return BFS_ERR_ARG;
   if (!p->began || p->finished) return p->fail(BFS_ERR_STATE, "bfs_expand before bfs_begin");
@@ -330,6 +349,8 @@ bfs_status bfs_expand(bfs_plan_t p, const uint64_t **local_next) {
     if (e != hipSuccess) return p->hip_fail(e, "stats launch");
   }
   if (p->expanded_level == p->level) return p->fail(BFS_ERR_STATE, "level already expanded");
+  bfs_status fs = fill_stale_queues(p, v);
+  if (fs) return fs;
   const bool timed = p->time_levels && p->level < Plan::kTimedLevels;
   if (timed) {
     p->level_kind[p->level] = 0;
@@ -366,7 +387,7 @@ bfs_status bfs_expand_bottom_up(bfs_plan_t p, const uint64_t **local_next) {
   }
   // level 0: the frontier is the root alone, which is what `visited` holds
   const uint64_t *front = p->level == 0 ? v.visited : v.front;
-  hipError_t e = launch_bottom_up(v, p->level, p->num_cus * std::max(p->bpc_bu, 1), 0u, front, p->stream);
+  hipError_t e = launch_bottom_up(v, p->level, p->num_cus * std::max(p->bpc_bu, 1), 0u, front, 0, p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "bottom-up launch");
   if (timed) (void)hipEventRecord(p->lev[p->level][1], p->stream);
   p->expanded_level = p->level;
@@ -393,6 +414,7 @@ bfs_status bfs_merge_frontier(bfs_plan_t p, const uint64_t *const *incoming, int
     done += chunk;
     a.keep_next = (done < k || keep_next) ? 1 : 0;
     a.level = p->level;
+    a.mode = p->merge_mode;
     hipError_t e = launch_merge(v, a, p->merge_grid(v.words), p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "merge launch");
   } while (done < k);
@@ -484,6 +506,8 @@ bfs_status queue_only_level(bfs_plan_t p, int64_t *global_new) {
     hipError_t e = launch_clear_stats_row(v, p->level + 1, p->stream);
     if (e != hipSuccess) return p->hip_fail(e, "stats launch");
   }
+  bfs_status fs = fill_stale_queues(p, v);
+  if (fs) return fs;
   const bool timed = p->time_levels && p->level < Plan::kTimedLevels;
   if (timed) {
     p->level_kind[p->level] = 1;
@@ -526,13 +550,23 @@ bfs_status bottom_up_level(bfs_plan_t p, int64_t *global_new) {
   hipError_t e = hipSuccess;
   if (p->front_level != p->level) e = launch_front_from_queues(v, p->level, p->wide_grid(), p->stream);
   const uint32_t hot = (uint32_t)std::min<int64_t>(kBottomUpHot, v.words);
+  // The next level reads the frontier bitmap if it is bottom-up too, so the
+  // merge leaves the tier queues unwritten and the step counts the new
+  // vertices' edges; a top-down level fills the queues first (with stats on,
+  // the merge's degree histogram needs the full merge).
+  const bool no_queues = !p->opt.collect_stats;
   if (e == hipSuccess)
-    e = launch_bottom_up(v, p->level, p->num_cus * std::max(p->bpc_bu, 1), hot, v.front, p->stream);
+    e = launch_bottom_up(v, p->level, p->num_cus * std::max(p->bpc_bu, 1), hot, v.front, no_queues ? 1 : 0,
+                         p->stream);
   if (e != hipSuccess) return p->hip_fail(e, "bottom-up launch");
   if (timed) (void)hipEventRecord(p->lev[p->level][1], p->stream);
   p->expanded_level = p->level;
   p->bu_levels_run += 1;
-  return bfs_merge_frontier(p, nullptr, 0, 0, global_new, nullptr);
+  p->merge_mode = no_queues ? kMergeNoQueues : kMergeFull;
+  bfs_status st = bfs_merge_frontier(p, nullptr, 0, 0, global_new, nullptr);
+  p->merge_mode = kMergeFull;
+  if (st == BFS_OK && no_queues) p->queues_stale = true;
+  return st;
 }
 
 }  // namespace

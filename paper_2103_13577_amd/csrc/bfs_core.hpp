@@ -84,11 +84,19 @@ struct View {
 
 constexpr int kMaxIncoming = 8;  // received bitmaps per merge launch
 
+// Merge modes: the ordinary merge; a merge that leaves the next level's tier
+// queues unwritten (after a bottom-up step, whose successor reads the frontier
+// bitmap; the step counts the new vertices' edges itself); and a pass that
+// only fills those queues from the frontier bitmap, for a top-down level that
+// follows such a merge.
+constexpr int32_t kMergeFull = 0, kMergeNoQueues = 1, kMergeQueuesFromFront = 2;
+
 struct MergeArgs {
   const uint64_t *inc[kMaxIncoming];  // received bitmaps (device)
   int32_t k;
   int32_t keep_next;
   int32_t level;
+  int32_t mode;  // kMerge*
 };
 
 // Degree bin: 0 for degree 0, else 1 + floor(log2(degree)).
@@ -118,7 +126,7 @@ hipError_t enqueue_graph_levels(const View &v, int levels, int max_levels, int e
 int persistent_blocks_per_cu(int variant);
 int expand_blocks_per_cu(uint32_t hot_words);
 hipError_t launch_bottom_up(const View &v, int level, int grid, uint32_t hot_words, const uint64_t *front,
-                            hipStream_t s);
+                            int count_edges, hipStream_t s);
 hipError_t launch_front_from_queues(const View &v, int level, int grid, hipStream_t s);
 int bottom_up_blocks_per_cu(uint32_t hot_words);
 size_t cu_lds_bytes(int64_t words);

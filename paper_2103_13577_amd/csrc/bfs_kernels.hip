@@ -465,6 +465,9 @@ __device__ __forceinline__ uint64_t owned_mask(int64_t w, int64_t vb, int64_t ve
   return m;
 }
 
+// MODE is a kMerge* constant (the ordinary merge compiles without the other
+// modes' branches).
+template <int MODE>
 __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const MergeArgs &a,
                                             uint32_t vb_id, uint32_t nvb) {
   __shared__ uint32_t s_cnt[kWavesPerBlock][3];
@@ -492,7 +495,13 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
     const int64_t wbase = g0 + wave * kWave;  // first word of this wavefront
     const int64_t w = wbase + lane;
     uint64_t nw = 0, om = 0;
-    if (w < v.words && v.into_vis) {
+    if (MODE == kMergeQueuesFromFront) {
+      if (w < v.words) {
+        const uint64_t tail = (w == v.words - 1 && (v.n & 63)) ? ~0ull >> (64 - (v.n & 63)) : ~0ull;
+        nw = v.front[w] & tail;
+        om = nw & owned_mask(w, v.vb, v.ve);
+      }
+    } else if (w < v.words && v.into_vis) {
       // the expansion ORed into `visited`; `next` holds visited as it was at
       // the level's start, and becomes the current visited
       const uint64_t vis = v.visited[w], prev = v.next[w];
@@ -519,7 +528,7 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
       if (v.front && !a.keep_next) v.front[w] = m & tail;
       om = nw & owned_mask(w, v.vb, v.ve);
     }
-    my_new += (uint64_t)__popcll(nw);
+    if (MODE != kMergeQueuesFromFront) my_new += (uint64_t)__popcll(nw);
     // A workgroup step without new vertices (the common case on sparse
     // levels) has no distances, queue entries or counters to write.
     if (!__syncthreads_or(nw != 0ull)) continue;
@@ -529,10 +538,13 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
     // row-offset loads of eight words are in flight together.
     uint64_t t1m = 0, t2m = 0;
     uint64_t chunks = 0;  // wave-uniform
+    constexpr bool write_dist = MODE != kMergeQueuesFromFront;
+    constexpr bool tiers = MODE != kMergeNoQueues;
     uint64_t act = ballot(nw != 0);
     if (ballot(om != 0) == 0ull) {
       // no owned new vertex in this wavefront's words (a node's share covers
       // a fraction of the bitmap): distances only, one word per step
+      if (!write_dist) act = 0;
       while (act) {
         const int j = __ffsll((unsigned long long)act) - 1;
         act &= act - 1;
@@ -568,20 +580,25 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
       // an owned new vertex, so the owned range is not empty), so the
       // wavefront waits for memory once per batch rather than once per word.
       int32_t oid[kW];
-      if (v.old_id) {
+      if (v.old_id && write_dist) {
 #pragma unroll
         for (int q = 0; q < kW; ++q) oid[q] = v.old_id[min(vtx[q], v.n - 1)];
       }
       const int64_t nloc = v.ve - v.vb;
+      if (tiers) {
 #pragma unroll
-      for (int q = 0; q < kW; ++q) {
-        const int64_t li = min(max(vtx[q] - v.vb, (int64_t)0), nloc - 1);
-        r0[q] = v.rp[li];
-        r1[q] = v.rp[li + 1];
+        for (int q = 0; q < kW; ++q) {
+          const int64_t li = min(max(vtx[q] - v.vb, (int64_t)0), nloc - 1);
+          r0[q] = v.rp[li];
+          r1[q] = v.rp[li + 1];
+        }
       }
+      if (write_dist) {
 #pragma unroll
-      for (int q = 0; q < kW; ++q)
-        if (isnew[q]) dist[v.old_id ? (int64_t)oid[q] : vtx[q]] = dnew;
+        for (int q = 0; q < kW; ++q)
+          if (isnew[q]) dist[v.old_id ? (int64_t)oid[q] : vtx[q]] = dnew;
+      }
+      if (!tiers) continue;
 #pragma unroll
       for (int q = 0; q < kW; ++q) {
         if (q >= cnt) break;
@@ -590,8 +607,10 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
         if (own[q]) {
           const int b = degree_bin(deg);
           t = tier_of_bin(b, v.small_bin, v.wave_bin);
-          my_edges += (uint64_t)deg;
-          if (v.stats) atomicAdd(&s_hist[b], 1u);
+          if (MODE == kMergeFull) {
+            my_edges += (uint64_t)deg;
+            if (v.stats) atomicAdd(&s_hist[b], 1u);
+          }
         }
         const uint64_t m1 = ballot(own[q] && t == 1);
         const uint64_t m2 = ballot(own[q] && t == 2);
@@ -602,10 +621,15 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
         }
       }
     }
+    if (!tiers) {
+      // no queues: the owned new vertices are only counted
+      my_owned += (uint64_t)__popcll(om);
+      continue;
+    }
     const uint32_t c0 = wave_sum_u32((uint32_t)__popcll(om & ~t1m & ~t2m));
     const uint32_t c1 = wave_sum_u32((uint32_t)__popcll(t1m));
     const uint32_t c2 = wave_sum_u32((uint32_t)__popcll(t2m));
-    my_owned += (lane == 0) ? (uint64_t)(c0 + c1 + c2) : 0ull;
+    if (MODE == kMergeFull) my_owned += (lane == 0) ? (uint64_t)(c0 + c1 + c2) : 0ull;
 
     // Workgroup aggregation: one atomic per tier per workgroup step.
     if (lane == 0) {
@@ -755,8 +779,9 @@ __global__ void __launch_bounds__(kWideBlock) k_expand_wide(View v, int level, u
       v, v.dist, level, blockIdx.x, gridDim.x, load_hot<kWideBlock>(v, s_hot, hot_words));
 }
 
+template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_merge(View v, MergeArgs a) {
-  merge_phase(v, v.dist, a, blockIdx.x, gridDim.x);
+  merge_phase<MODE>(v, v.dist, a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -775,10 +800,12 @@ constexpr int kBuUnroll = 4;  // adjacency entries per lane in flight
 // and the next frontier bitmap). The first frontier words are copied to LDS:
 // on a relabelled graph every adjacency list starts with the hubs, so the
 // first probes of most lanes are LDS reads.
+// count_edges: also add the degrees of the vertices found to the traversal's
+// edge count (for a merge that leaves the tier queues unwritten).
 __global__ void __launch_bounds__(kBlock) k_bottom_up(View v, int level, uint32_t hot_words,
-                                                      const uint64_t *front) {
+                                                      const uint64_t *front, int count_edges) {
   extern __shared__ uint64_t s_hot[];
-  __shared__ uint64_t s_acc[2][kWavesPerBlock];
+  __shared__ uint64_t s_acc[3][kWavesPerBlock];
   const int lane = lane_id();
   const uint32_t wave = threadIdx.x / kWave;
   const uint64_t gwave = (uint64_t)blockIdx.x * kWavesPerBlock + wave;
@@ -794,7 +821,7 @@ __global__ void __launch_bounds__(kBlock) k_bottom_up(View v, int level, uint32_
   const uint32_t hw = (uint32_t)min<int64_t>(hot_words, v.words);
   for (uint32_t i = threadIdx.x; i < hw; i += kBlock) s_hot[i] = front[i];
   __syncthreads();
-  uint64_t examined = 0, verts = 0;
+  uint64_t examined = 0, verts = 0, found_edges = 0;
   // vertices without an edge are never found: a relabelled graph keeps them
   // after live_end, and their words are skipped
   const uint64_t wb = (uint64_t)(v.vb >> 6), we = (uint64_t)((min(v.ve, v.live_end) + 63) >> 6);
@@ -833,25 +860,30 @@ __global__ void __launch_bounds__(kBlock) k_bottom_up(View v, int level, uint32_
     if (todo) {
       examined += (uint64_t)(min(k, e) - k0);
       verts += 1;
+      if (found) found_edges += (uint64_t)(e - k0);
     }
     const uint64_t fm = ballot(found);
     if (lane == 0 && fm) v.next[w] = fm;
   }
   const uint64_t te = (uint64_t)wave_sum((int64_t)examined);
   const uint64_t tv = (uint64_t)wave_sum((int64_t)verts);
+  const uint64_t tf = (uint64_t)wave_sum((int64_t)found_edges);
   if (lane == 0) {
     s_acc[0][wave] = te;
     s_acc[1][wave] = tv;
+    s_acc[2][wave] = tf;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint64_t a = 0, b = 0;
+    uint64_t a = 0, b = 0, f = 0;
     for (int i = 0; i < kWavesPerBlock; ++i) {
       a += s_acc[0][i];
       b += s_acc[1][i];
+      f += s_acc[2][i];
     }
     if (a) atomic_add64(&v.ctl->buedges, a);
     if (b) atomic_add64(&v.ctl->buverts, b);
+    if (f && count_edges) atomic_add64(&v.ctl->edges, f);
   }
 }
 
@@ -929,7 +961,8 @@ __global__ void __launch_bounds__(kBlock) k_merge_g(View v) {
   a.k = 0;
   a.keep_next = 0;
   a.level = L;
-  merge_phase(v, v.ctl->gdist, a, blockIdx.x, gridDim.x);
+  a.mode = kMergeFull;
+  merge_phase<kMergeFull>(v, v.ctl->gdist, a, blockIdx.x, gridDim.x);
 }
 
 // One thread: termination test and level advance; clears the histogram row
@@ -977,6 +1010,7 @@ __device__ __forceinline__ void persistent_body(const View &v, int max_levels) {
   MergeArgs a;
   a.k = 0;
   a.keep_next = 0;
+  a.mode = kMergeFull;
   int L = 0;
   for (;; ++L) {
     // Row L+2 of the histogram is cleared a level ahead: rows L+1 are
@@ -1000,7 +1034,7 @@ __device__ __forceinline__ void persistent_body(const View &v, int max_levels) {
       expand_phase<false>(v, v.dist, L, blockIdx.x, nb);
       grid_barrier(&v.ctl->bar, nb);
       a.level = L;
-      merge_phase(v, v.dist, a, blockIdx.x, nb);
+      merge_phase<kMergeFull>(v, v.dist, a, blockIdx.x, nb);
       grid_barrier(&v.ctl->bar, nb);
     }
     const uint64_t nn = load_relaxed64(&v.ctl->newcnt[L % 3]);
@@ -1084,7 +1118,13 @@ hipError_t launch_expand(const View &v, int level, int grid, uint32_t hot_words,
 }
 
 hipError_t launch_merge(const View &v, const MergeArgs &a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_merge, dim3(grid), dim3(kBlock), 0, s, v, a);
+  switch (a.mode) {
+    case kMergeNoQueues: hipLaunchKernelGGL(k_merge<kMergeNoQueues>, dim3(grid), dim3(kBlock), 0, s, v, a); break;
+    case kMergeQueuesFromFront:
+      hipLaunchKernelGGL(k_merge<kMergeQueuesFromFront>, dim3(grid), dim3(kBlock), 0, s, v, a);
+      break;
+    default: hipLaunchKernelGGL(k_merge<kMergeFull>, dim3(grid), dim3(kBlock), 0, s, v, a); break;
+  }
   return hipGetLastError();
 }
 
@@ -1099,9 +1139,9 @@ hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, 
 }
 
 hipError_t launch_bottom_up(const View &v, int level, int grid, uint32_t hot_words, const uint64_t *front,
-                            hipStream_t s) {
+                            int count_edges, hipStream_t s) {
   hipLaunchKernelGGL(k_bottom_up, dim3(grid), dim3(kBlock), (size_t)hot_words * 8, s, v, level, hot_words,
-                     front);
+                     front, count_edges);
   return hipGetLastError();
 }
 

@@ -106,6 +106,8 @@ struct bfs_plan_s {
   bool cur_into_vis = false;          // dense expansions OR into `visited` (see View::into_vis)
   bool bu_state = false;              // the current level runs bottom-up
   int front_level = -1;               // level whose frontier the front bitmap holds
+  int32_t merge_mode = 0;             // mode of bfs_merge_frontier's merge (bfs_run's bottom-up levels)
+  bool queues_stale = false;          // the last merge left the tier queues unwritten
   std::vector<int64_t> edges_after;   // edge counter (sum of reached degrees) after each level
   int bpc_bu = 0;                     // co-resident bottom-up blocks per CU
   bool direction_optimizing(int32_t gi) const {
