@@ -178,6 +178,44 @@ def test_direction_optimizing_exact(gpu, opts):
         plan.close()
 
 
+@pytest.mark.parametrize("opts", [dict(), dict(sparse_div=-1)])
+def test_direction_optimizing_returns_top_down(gpu, opts):
+    """Top-down levels after bottom-up ones: the merges that finish bottom-up
+    levels leave the tier queues unwritten (the step counts the found
+    vertices' edges), and the next top-down level (queue-only, or dense with
+    sparse_div=-1) fills them from the frontier bitmap. An R-MAT core with a
+    40-vertex path hanging off a vertex at the core's largest distance from the
+    source: the core's large levels run bottom-up, and top-down levels follow
+    on the path."""
+    core = gg.rmat(14, 16, seed=91, perm_seed=92)
+    src = int(gg.pick_sources(core, 1, seed=93)[0])
+    far = int(np.argmax(oracle.bfs(core, src)))
+    rows = np.repeat(np.arange(core.n, dtype=np.int64), np.diff(core.row_ptr))
+    edges = np.stack([rows, core.col.astype(np.int64)], 1)
+    edges = edges[edges[:, 0] < edges[:, 1]]
+    path = np.array([(far, core.n)] + [(core.n + i, core.n + i + 1) for i in range(39)], dtype=np.int64)
+    g = gg.from_edges(core.n + 40, np.concatenate([edges, path]), "rmat14_path40")
+    ref = oracle.bfs(g, src)
+    assert ref[core.n + 39] == ref[far] + 40
+    dg = pkg.DeviceGraph.from_csr(g, gpu)
+    plan = pkg.Plan([dg], direction=pkg.DIR_OPTIMIZING, **opts)
+    assert plan.tuning(0)["direction"] == pkg.DIR_OPTIMIZING
+    for rep in range(2):  # the second traversal starts from the first one's state
+        print(f"[gpu] DO core+path src={src} rep={rep} {opts}", flush=True)
+        d, par, st = plan.run(0, src, parent=True)
+        assert np.array_equal(d.cpu().numpy(), ref)
+        assert np.array_equal(par.cpu().numpy(), oracle.parent(g, ref))
+        assert st.edges_scanned == oracle.edges_scanned(g, ref)
+        assert st.reached == int((ref >= 0).sum())
+        assert st.levels == int(ref.max()) + 1
+        # levels 0 and 1 run top-down and the core's largest level (2, else 3)
+        # bottom-up (its frontier's edges are 13x the unvisited edges), so more
+        # than three top-down levels include some after the bottom-up ones
+        assert st.bottom_up_levels > 0
+        assert st.levels - st.bottom_up_levels > 3
+    plan.close()
+
+
 def test_dense_work_accounting(gpu):
     """The device's count of the work behind the dense expansions (the bytes
     the benchmark's roofline figure divides by their time): with every level
