@@ -182,6 +182,9 @@ bfs_status bfs_workspace_size(const bfs_graph *graphs, int32_t ngraphs, const bf
  * arrays they point to must outlive the plan). workspace: device memory of at
  * least bfs_workspace_size() bytes, 256-byte aligned, owned by the caller.
  * Autotuned tier thresholds are chosen here when the options leave them 0.
+ * Besides the host object, the plan holds HIP events, a capture stream and a
+ * small pinned host buffer (the host copy of its control block, read after
+ * each level of the host-driven loop); bfs_plan_destroy releases them.
  */
 bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_options *o,
                            void *workspace, size_t ws_bytes, bfs_plan_t *out);
