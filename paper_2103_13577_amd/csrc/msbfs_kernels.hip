@@ -212,6 +212,31 @@ __device__ __forceinline__ bool ms_update_vertex(const MsView &v, int L, bool va
       atomicOr((unsigned long long *)&sh.s_or[g * LW + l], (unsigned long long)nw[l]);
     }
     uint64_t wor = wave_or(nw[l]);
+    if (uniform_graph && wor) {
+      // one graph: lane k holds slot k's start level, output and type, and
+      // each slot bit reads them from that lane (no memory wait per bit)
+      const int sbase = (g * LW + l) * 64;
+      const int32_t my_start = v.slot_start[sbase + lane];
+      const uint64_t my_out = v.slot_out[sbase + lane];
+      const int32_t my_type = v.slot_type[sbase + lane];
+      while (wor) {
+        const int b = __ffsll((unsigned long long)wor) - 1;
+        wor &= wor - 1;
+        const int32_t val = L + 1 - __builtin_amdgcn_readlane(my_start, b);
+        const uint64_t ptr = readlane64(my_out, b);
+        const int32_t type = __builtin_amdgcn_readlane(my_type, b);
+        if ((nw[l] >> b) & 1ull) {
+          // outputs are device memory: global stores, not generic (flat) ones
+          if (type == 0) {
+            if (val > 254) atomic_or64(&v.depth_err[g * LW + l], 1ull << b);
+            else ((__attribute__((address_space(1))) uint8_t *)ptr)[xl] = (uint8_t)val;
+          } else if (type == 1) {
+            ((__attribute__((address_space(1))) int32_t *)ptr)[xl] = val;
+          }
+        }
+      }
+      continue;
+    }
     while (wor) {
       const int b = __ffsll((unsigned long long)wor) - 1;
       wor &= wor - 1;
