@@ -209,18 +209,23 @@ bfs_status batch_autotune(Plan *p, BatchState *b, int bpc) {
   };
   bfs_status s = trial(best);
   const int cus = p->num_cus;
-  if (!s && p->opt.grid_blocks <= 0)
-    for (int g : {cus, 2 * cus, std::min(bpc, 8) * cus}) {
-      Setting c = best;
-      c.grid = g;
-      if ((s = trial(c))) break;
+  // grid and tier-0 threshold together: the best grid depends on the
+  // threshold (fewer, longer tier-0 batches suit a smaller grid), so tuning
+  // them one after the other can stop at the worse pair
+  {
+    const Setting start = best;
+    std::vector<int> grids{start.grid}, sbs{start.small_bin};
+    if (p->opt.grid_blocks <= 0) grids = {cus, 2 * cus, std::min(bpc, 8) * cus};
+    if (p->opt.small_bin <= 0) sbs = {4, 8};
+    for (int g : grids) {
+      for (int sb : sbs) {
+        Setting c = start;
+        c.grid = g;
+        c.small_bin = sb;
+        if (!s) s = trial(c);
+      }
     }
-  if (!s && p->opt.small_bin <= 0)
-    for (int sb : {4, 8}) {
-      Setting c = best;
-      c.small_bin = sb;
-      if ((s = trial(c))) break;
-    }
+  }
   if (!s && p->opt.wave_bin <= 0)
     for (int wb : {11, 15}) {
       Setting c = best;
