@@ -127,7 +127,13 @@ typedef struct {
                               exchange callback may run large levels bottom-up (see below),
                               and step-wise traversals may call bfs_expand_bottom_up.
                               Distances are the same either way */
-  int32_t reserved;
+  int32_t mark_mode;       /* bfs_run on a whole graph without queue-only or bottom-up levels:
+                              0 or 1 = byte marks: the expansion leaves the bitmaps alone,
+                              keeps the hubs it finds in its LDS copy of their visited bits
+                              (ORed into a small hub bitmap once per workgroup) and sets one
+                              byte per other candidate with a plain store; the merge folds
+                              both into the visited bitmap. -1 = the expansion ORs bits into
+                              the visited bitmap with device-scope atomics */
 } bfs_options;
 
 #define BFS_DIR_TOPDOWN 0
@@ -211,6 +217,7 @@ typedef struct {
   int32_t sparse_div;       /* single node: a level runs queue-only when its frontier is below
                                ceil(n/64) / sparse_div (0: never) */
   int32_t direction;        /* BFS_DIR_* the traversal of this graph uses */
+  int32_t mark_mode;        /* 1: dense levels set byte marks, -1: atomic ORs into a bitmap */
 } bfs_tuning;
 
 /* Fills *out (host) with the settings of graph `graph`. */
@@ -315,6 +322,20 @@ bfs_status bfs_merge_lists(bfs_plan_t p, const int32_t *const *lists, const int6
  */
 bfs_status bfs_level_stats(bfs_plan_t p, int64_t *frontier, int64_t *hist, int32_t max_levels,
                            int32_t *levels);
+
+/*
+ * Per-level device times of the last bfs_run when it drove the host loop
+ * (HIP events around each launch, first BFS_MAX_TIMED_LEVELS levels):
+ * expand_ms[L] = Phase 1 of level L (the top-down expansion, the queue-only
+ * level or the bottom-up step), merge_ms[L] = its Phase 2 merge (0 for a
+ * queue-only level, which has none), kind[L] = 0 top-down with a bitmap
+ * merge, 1 queue-only, 2 bottom-up. Host arrays of max_levels entries (each
+ * may be NULL); *levels (host, may be NULL) receives the number of timed
+ * levels, 0 when the last traversal ran another loop.
+ */
+#define BFS_MAX_TIMED_LEVELS 64
+bfs_status bfs_level_times(bfs_plan_t p, float *expand_ms, float *merge_ms, int32_t *kind,
+                           int32_t max_levels, int32_t *levels);
 
 /* ------------------------------------------------------------------------ */
 /* Batched multi-source traversal and serving                               */

@@ -46,7 +46,7 @@ class bfs_options(ctypes.Structure):
                 ("exchange", EXCHANGE_FN), ("exchange_ctx", ctypes.c_void_p),
                 ("relabel", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("hot_words", ctypes.c_int32), ("sparse_div", ctypes.c_int32),
-                ("direction", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("direction", ctypes.c_int32), ("mark_mode", ctypes.c_int32)]
 
 
 class bfs_stats(ctypes.Structure):
@@ -66,7 +66,7 @@ class bfs_tuning(ctypes.Structure):
                 ("wave_bin", ctypes.c_int32), ("chunk_edges", ctypes.c_int32),
                 ("relabelled", ctypes.c_int32), ("tuned_ms", ctypes.c_float),
                 ("hot_words", ctypes.c_int32), ("sparse_div", ctypes.c_int32),
-                ("direction", ctypes.c_int32)]
+                ("direction", ctypes.c_int32), ("mark_mode", ctypes.c_int32)]
 
 
 class bfs_query(ctypes.Structure):
@@ -107,6 +107,7 @@ def lib():
                                      ctypes.POINTER(i64)]),
         "bfs_finish": (i32, [vp, vp, ctypes.POINTER(bfs_stats)]),
         "bfs_level_stats": (i32, [vp, vp, vp, i32, ctypes.POINTER(i32)]),
+        "bfs_level_times": (i32, [vp, vp, vp, vp, i32, ctypes.POINTER(i32)]),
         "bfs_plan_tuning": (i32, [vp, i32, ctypes.POINTER(bfs_tuning)]),
         "bfs_batch_submit": (i32, [vp, ctypes.POINTER(bfs_query), i32, u32, ctypes.POINTER(u64)]),
         "bfs_batch_wait": (i32, [vp, u64, i64, ctypes.POINTER(bfs_batch_result)]),
@@ -129,7 +130,7 @@ def lib():
 
 EXPORTED = ("bfs_options_default", "bfs_workspace_size", "bfs_plan_create", "bfs_plan_destroy",
             "bfs_last_error", "bfs_run", "bfs_begin", "bfs_expand", "bfs_merge_frontier",
-            "bfs_finish", "bfs_level_stats", "bfs_plan_tuning", "bfs_batch_submit",
+            "bfs_finish", "bfs_level_stats", "bfs_level_times", "bfs_plan_tuning", "bfs_batch_submit",
             "bfs_batch_wait", "bfs_batch_times", "bfs_batch_poll", "bfs_batch_tuning",
             "bfs_frontier_list", "bfs_merge_lists", "bfs_expand_bottom_up")
 
@@ -205,7 +206,7 @@ class Plan:
 
     def __init__(self, graphs, *, loop_mode=LOOP_AUTO, small_bin=0, wave_bin=0, chunk_edges=0,
                  grid_blocks=0, batch_lanes=0, collect_stats=False, exchange=None, stream=None,
-                 relabel=0, autotune=0, hot_words=0, sparse_div=0, direction=0):
+                 relabel=0, autotune=0, hot_words=0, sparse_div=0, direction=0, mark_mode=0):
         torch = _torch()
         L = lib()
         if isinstance(graphs, DeviceGraph):
@@ -224,6 +225,7 @@ class Plan:
         o.hot_words = int(hot_words)
         o.sparse_div = int(sparse_div)
         o.direction = int(direction)
+        o.mark_mode = int(mark_mode)
         self._exchange_py = exchange
         self._exchange_keep = None
         if exchange is not None:
@@ -368,6 +370,18 @@ class Plan:
         self._check(lib().bfs_level_stats(self.h, f.ctypes.data, h.ctypes.data, MAX_LEVEL_STATS,
                                           ctypes.byref(nl)))
         return f[:nl.value].copy(), h[:nl.value].copy()
+
+    def level_times(self):
+        """(Phase 1 ms, Phase 2 ms, kind) per level of the last host-driven
+        traversal (kind 0 top-down, 1 queue-only, 2 bottom-up)."""
+        n = 64
+        a = np.zeros(n, dtype=np.float32)
+        b = np.zeros(n, dtype=np.float32)
+        k = np.zeros(n, dtype=np.int32)
+        nl = ctypes.c_int32(0)
+        self._check(lib().bfs_level_times(self.h, a.ctypes.data, b.ctypes.data, k.ctypes.data, n,
+                                          ctypes.byref(nl)))
+        return a[:nl.value].copy(), b[:nl.value].copy(), k[:nl.value].copy()
 
     # -- batched / serving -----------------------------------------------------
     def batch_submit(self, queries, flags=BATCH_ONE_LAUNCH) -> int:

@@ -53,8 +53,20 @@ void layout_single(const bfs_graph *g, int32_t ng, WsLayout &L, size_t &off) {
   L.visited = off; off = align_up(off + sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), 256);
   L.next = off; off = align_up(off + sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), 256);
   L.front = off; off = align_up(off + sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), 256);
+  // byte marks of dense single-node levels, 64 per bitmap word (whole graphs only)
+  int64_t whole_words = 0;
+  for (int i = 0; i < ng; ++i)
+    if (g[i].v_begin == 0 && g[i].v_end == g[i].n_global)
+      whole_words = std::max(whole_words, (g[i].n_global + 63) / 64);
+  L.mark = 0;
+  if (whole_words > 0) {
+    L.mark = off; off = align_up(off + 64 * (size_t)whole_words, 256);
+    L.hubnext = off; off = align_up(off + sizeof(uint64_t) * kMaxHotWords, 256);
+  }
   for (int t = 0; t < 3; ++t)
     for (int p = 0; p < kRing; ++p) { L.q[t][p] = off; off = align_up(off + sizeof(int32_t) * (size_t)omax, 256); }
+  for (int t = 0; t < 2; ++t)
+    for (int p = 0; p < kRing; ++p) { L.qr[t][p] = off; off = align_up(off + sizeof(uint64_t) * (size_t)omax, 256); }
   for (int p = 0; p < kRing; ++p) { L.cstart[p] = off; off = align_up(off + sizeof(uint32_t) * (size_t)omax, 256); }
 }
 
@@ -90,6 +102,8 @@ View bfs_plan_s::view(int32_t gi, int32_t *dist) const {
     v.q0[p] = (int32_t *)(b + lay.q[0][p]);
     v.q1[p] = (int32_t *)(b + lay.q[1][p]);
     v.q2[p] = (int32_t *)(b + lay.q[2][p]);
+    v.qr0[p] = (uint64_t *)(b + lay.qr[0][p]);
+    v.qr1[p] = (uint64_t *)(b + lay.qr[1][p]);
     v.cstart[p] = (uint32_t *)(b + lay.cstart[p]);
   }
   v.ctl = (Ctl *)(b + lay.ctl);
@@ -101,6 +115,9 @@ View bfs_plan_s::view(int32_t gi, int32_t *dist) const {
   v.stats = opt.collect_stats ? 1 : 0;
   v.sparse_div = tune[gi].sparse_div;
   v.into_vis = cur_into_vis ? 1 : 0;
+  v.mark = cur_mark ? (uint8_t *)(b + lay.mark) : nullptr;
+  v.hubnext = cur_mark ? (uint64_t *)(b + lay.hubnext) : nullptr;
+  v.hub_words = v.hubnext ? kMaxHotWords : 0;
   return v;
 }
 
@@ -170,7 +187,7 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
   for (int i = 0; i < ngraphs; ++i) {
     const bfs_graph &g = graphs[i];
     if (g.n_global <= 0 || g.n_global >= (1ll << 31) || g.v_begin < 0 || g.v_end < g.v_begin ||
-        g.v_end > g.n_global || g.m < 0 || !g.row_ptr || (g.m > 0 && !g.col)) {
+        g.v_end > g.n_global || g.m < 0 || g.m >= (1ll << 40) || !g.row_ptr || (g.m > 0 && !g.col)) {
       g_create_error = "graph " + std::to_string(i) + ": bad sizes or null pointers";
       return BFS_ERR_ARG;
     }
@@ -258,6 +275,8 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
   if (st) { g_create_error = p->err; delete p; return st; }
   st = autotune_graphs(p);
   if (st) { g_create_error = p->err; delete p; return st; }
+  st = prepare_run_loops(p);
+  if (st) { g_create_error = p->err; delete p; return st; }
   st = batch_init(p);
   if (st) { g_create_error = p->err; delete p; return st; }
   *out = p;
@@ -267,6 +286,9 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
 void bfs_plan_destroy(bfs_plan_t p) {
   if (!p) return;
   batch_shutdown(p);
+  // work queued on the plan's streams ends before its graphs and events go
+  (void)hipStreamSynchronize(p->stream);
+  if (p->cap_stream) (void)hipStreamSynchronize(p->cap_stream);
   delete p;
 }
 
@@ -298,6 +320,7 @@ bfs_status begin_impl(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist
   p->cur_front = p->cur_do || (!relabel && p->opt.direction == BFS_DIR_OPTIMIZING);
   p->bu_state = false;
   p->cur_into_vis = false;
+  p->cur_mark = false;
   p->front_level = -1;
   p->merge_mode = kMergeFull;
   p->queues_stale = false;
@@ -607,7 +630,7 @@ namespace {
 
 bool same_tuning(const Tuning &a, const Tuning &b) {
   return a.small_bin == b.small_bin && a.wave_bin == b.wave_bin && a.chunk_shift == b.chunk_shift &&
-         a.sparse_div == b.sparse_div && a.hot_words == b.hot_words;
+         a.sparse_div == b.sparse_div && a.hot_words == b.hot_words && a.mark == b.mark;
 }
 
 // The captured graph of kGraphLevels level steps for graph gi (captured on
@@ -655,9 +678,36 @@ namespace {
 // straight into `visited` (one bitmap for their random probes instead of two);
 // `next` then holds visited as of each level's start, from which the merge
 // finds the new vertices. Called after the reset, before the level loop.
+// With byte marks (a whole graph whose tuning selects them) the expansions
+// leave both bitmaps alone and set one byte per discovered vertex instead;
+// the marks must all be zero when the traversal starts.
+// The expansion form bfs_run uses for a graph (its flags only; no device
+// work): byte marks, an OR into `visited`, or neither (queue-only levels,
+// bottom-up levels or an exchange keep the two-bitmap form).
+void dense_form(bfs_plan_t p, int32_t graph) {
+  p->cur_mark = p->cur_into_vis = false;
+  if (p->opt.exchange || p->cur_do || p->tune[graph].sparse_div != 0) return;
+  const bfs_graph &g = p->graphs[graph];
+  if (p->tune[graph].mark && p->lay.mark && g.v_begin == 0 && g.v_end == g.n_global)
+    p->cur_mark = true;
+  else
+    p->cur_into_vis = true;
+}
+
 bfs_status into_visited(bfs_plan_t p, int32_t graph, int32_t *dist) {
-  if (p->opt.exchange || p->cur_do || p->tune[graph].sparse_div != 0) return BFS_OK;
-  p->cur_into_vis = true;
+  dense_form(p, graph);
+  if (!p->cur_mark && !p->cur_into_vis) return BFS_OK;
+  if (p->cur_mark) {
+    if (!p->marks_clean) {
+      // the marks and the hub words that follow them
+      const size_t bytes = p->lay.hubnext + sizeof(uint64_t) * kMaxHotWords - p->lay.mark;
+      hipError_t e = hipMemsetAsync((char *)p->ws + p->lay.mark, 0, bytes, p->stream);
+      if (e != hipSuccess) return p->hip_fail(e, "clear marks");
+    }
+    // set again once the traversal has finished (its merges clear every mark)
+    p->marks_clean = false;
+    return BFS_OK;
+  }
   const View v = p->view(graph, dist);
   hipError_t e = hipMemcpyAsync(v.next, v.visited, sizeof(uint64_t) * (size_t)v.words,
                                 hipMemcpyDeviceToDevice, p->stream);
@@ -665,6 +715,7 @@ bfs_status into_visited(bfs_plan_t p, int32_t graph, int32_t *dist) {
 }
 
 }  // namespace
+
 
 bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, int32_t *parent,
                    bfs_stats *st) {
@@ -825,6 +876,8 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   }
   e = hipEventSynchronize(ev1);
   if (e != hipSuccess) return p->hip_fail(e, "hipEventSynchronize");
+  // a traversal that ran to its end left no mark set
+  if (p->cur_mark) p->marks_clean = true;
   float ms = 0.f, lms = 0.f;
   if (hipEventElapsedTime(&ms, ev0, ev1) != hipSuccess) ms = -1.f;
   if (hipEventElapsedTime(&lms, p->ev[2], ev1) != hipSuccess) lms = -1.f;
@@ -832,11 +885,17 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   p->last_loop_ms = lms;
   p->last_expand_ms = p->last_merge_ms = p->last_queue_ms = p->last_bu_ms = 0.f;
   p->last_expand_launches = 0;
+  p->timed_levels = 0;
   if (host_loop) {
     const int nl = std::min(p->level, Plan::kTimedLevels);
+    p->timed_levels = nl;
     for (int L = 0; L < nl; ++L) {
       float a = 0.f, b = 0.f;
       if (hipEventElapsedTime(&a, p->lev[L][0], p->lev[L][1]) != hipSuccess) a = 0.f;
+      if (hipEventElapsedTime(&b, p->lev[L][1], p->lev[L][2]) != hipSuccess) b = 0.f;
+      p->lev_ms[L][0] = a;
+      p->lev_ms[L][1] = p->level_kind[L] == 1 ? 0.f : b;
+      b = 0.f;
       if (p->level_kind[L] == 1) {
         p->last_queue_ms += a;
         continue;
@@ -874,6 +933,21 @@ bfs_status bfs_plan_tuning(bfs_plan_t p, int32_t graph, bfs_tuning *out) {
   out->hot_words = t.hot_words;
   out->sparse_div = t.sparse_div;
   out->direction = p->direction_optimizing(graph) ? BFS_DIR_OPTIMIZING : BFS_DIR_TOPDOWN;
+  out->mark_mode = t.mark ? 1 : -1;
+  return BFS_OK;
+}
+
+bfs_status bfs_level_times(bfs_plan_t p, float *expand_ms, float *merge_ms, int32_t *kind,
+                           int32_t max_levels, int32_t *levels) {
+  if (!p) return BFS_ERR_ARG;
+  if (!p->began) return p->fail(BFS_ERR_STATE, "no traversal yet");
+  if (levels) *levels = p->timed_levels;
+  const int cnt = std::min(p->timed_levels, std::max(max_levels, 0));
+  for (int L = 0; L < cnt; ++L) {
+    if (expand_ms) expand_ms[L] = p->lev_ms[L][0];
+    if (merge_ms) merge_ms[L] = p->lev_ms[L][1];
+    if (kind) kind[L] = p->level_kind[L];
+  }
   return BFS_OK;
 }
 
@@ -907,3 +981,33 @@ bfs_status bfs_level_stats(bfs_plan_t p, int64_t *frontier, int64_t *hist, int32
 }
 
 }  // extern "C"
+
+namespace bfsk {
+
+// Plan creation, after autotuning: everything bfs_run would otherwise set up
+// on first use. The captured level-step graph of every graph whose level loop
+// is the captured one is instantiated now, with the settings and expansion
+// form bfs_run uses, so bfs_run only replays it (no capture, instantiation
+// or allocation inside a traversal); the occupancy of the tuned expansion
+// kernels is queried here too.
+bfs_status prepare_run_loops(Plan *p) {
+  for (size_t gi = 0; gi < p->graphs.size(); ++gi) {
+    const Tuning &tu = p->tune[gi];
+    (void)p->expand_grid(tu.hot_words);
+    int mode = p->opt.loop_mode == BFS_LOOP_AUTO ? tu.loop_mode : p->opt.loop_mode;
+    if (p->opt.exchange || p->direction_optimizing((int32_t)gi)) mode = BFS_LOOP_HOST;
+    if (mode != BFS_LOOP_GRAPH) continue;
+    std::lock_guard<std::mutex> lk(p->run_mu);
+    p->cur_relabel = true;  // bfs_run's setting without an exchange callback
+    p->cur_do = false;
+    p->cur_front = false;
+    dense_form(p, (int32_t)gi);
+    hipGraphExec_t ge = nullptr;
+    bfs_status s = graph_exec(p, (int32_t)gi, ge);
+    p->cur_mark = p->cur_into_vis = false;
+    if (s) return s;
+  }
+  return BFS_OK;
+}
+
+}  // namespace bfsk

@@ -64,6 +64,8 @@ struct View {
                           // by every merge that finishes a level (NULL: off)
   int32_t *q0[kRing];
   int32_t *q1[kRing];
+  uint64_t *qr0[kRing];   // tier-0 / tier-1 queue entries' adjacency: (row start << 24) |
+  uint64_t *qr1[kRing];   // degree, written with q0 / q1 (tier degrees are below 2^24)
   int32_t *q2[kRing];
   uint32_t *cstart[kRing];
   Ctl *ctl;
@@ -80,9 +82,25 @@ struct View {
                           // and `next` holds visited as of the level's start
   int64_t live_end;       // owned vertices at or above it have no edge (a
                           // relabelled graph puts them last); else ve
+  uint8_t *mark;          // single-node dense levels: one byte per vertex, set to 1 by a
+                          // plain store when the expansion finds the vertex unvisited;
+                          // the merge folds each word's 64 bytes into a bit mask and
+                          // clears them (NULL: the expansion ORs bits atomically)
+  uint64_t *hubnext;      // mark mode: hub targets (those in an expansion block's LDS copy of
+                          // the hubs' visited words) found in the level, ORed in per block
+                          // at the end of the expansion; the merge folds and clears it
+  int32_t hub_words;      // words of hubnext the merge folds in (0: none)
 };
 
 constexpr int kMaxIncoming = 8;  // received bitmaps per merge launch
+constexpr int kMaxHotWords = 20480;  // largest LDS hub copy (160 KB)
+
+// Packed adjacency of a tier-0/1 queue entry: row start (below 2^40) and
+// degree (below 2^24).
+constexpr int kRowShift = 24;
+__host__ __device__ __forceinline__ uint64_t pack_row(int64_t start, int64_t deg) {
+  return ((uint64_t)start << kRowShift) | (uint64_t)deg;
+}
 
 // Merge modes: the ordinary merge; a merge that leaves the next level's tier
 // queues unwritten (after a bottom-up step, whose successor reads the frontier

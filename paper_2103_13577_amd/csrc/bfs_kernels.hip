@@ -70,8 +70,8 @@ __global__ void __launch_bounds__(kBlock) k_reset(View v, int64_t src_caller) {
       const int b = degree_bin(deg);
       const int t = tier_of_bin(b, v.small_bin, v.wave_bin);
       if (deg > 0) {
-        if (t == 0) { v.q0[0][0] = (int32_t)src; c->qn[0][0] = 1; }
-        else if (t == 1) { v.q1[0][0] = (int32_t)src; c->qn[0][1] = 1; }
+        if (t == 0) { v.q0[0][0] = (int32_t)src; v.qr0[0][0] = pack_row(v.rp[li], deg); c->qn[0][0] = 1; }
+        else if (t == 1) { v.q1[0][0] = (int32_t)src; v.qr1[0][0] = pack_row(v.rp[li], deg); c->qn[0][1] = 1; }
         else {
           v.q2[0][0] = (int32_t)src;
           v.cstart[0][0] = 0;
@@ -112,6 +112,29 @@ struct HotCache {
 };
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
+// Byte marks (View::mark): `visited` stays read-only during the level, so
+// the LDS copy of the hubs' words is exact at the level's start. A hub target
+// found unvisited is set in the block's LDS copy (an LDS atomic OR) and
+// nowhere else: the block ORs the bits it added into `hubnext` once, at the
+// end of the expansion, so hub targets cost no global traffic per edge. Every
+// other candidate target takes one plain byte store (repeated stores of the
+// same byte are harmless; no global atomic is issued per edge).
+template <int K>
+__device__ __forceinline__ void mark_targets(const View &v, const int32_t (&u)[K], const uint32_t (&w)[K],
+                                             const bool (&need)[K], HotCache hot) {
+  lds_u32 *hot32 = (lds_u32 *)(hot.lds);
+  const uint32_t hot_w32 = hot.words * 2;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    if (!need[j]) continue;
+    if (w[j] < hot_w32)
+      (void)__hip_atomic_fetch_or(hot32 + w[j], 1u << (u[j] & 31), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+      v.mark[(uint32_t)u[j]] = 1;
+  }
+}
+
 template <int K>
 __device__ __forceinline__ void probe_batch(const View &v, const int32_t (&u)[K],
                                             const bool (&ok)[K], HotCache hot) {
@@ -134,13 +157,20 @@ __device__ __forceinline__ void probe_batch(const View &v, const int32_t (&u)[K]
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     gv[j] = ~0u;
-    if (ok[j] && w[j] >= hot_w32) gv[j] = vis32[w[j]];
+    // mark mode with an LDS copy marks the other targets without reading
+    // `visited` (the merge drops those already visited): fewer scattered
+    // loads for a few more scattered stores, a net gain on R-MAT levels
+    if (ok[j] && w[j] >= hot_w32) gv[j] = (v.mark && hot_w32) ? 0u : vis32[w[j]];
   }
 #pragma unroll
   for (int j = 0; j < K; ++j) vis[j] = !ok[j] ? ~0u : (w[j] < hot_w32 ? lv[j] : gv[j]);
   bool need[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) need[j] = !((vis[j] >> (u[j] & 31)) & 1u);
+  if (v.mark) {
+    mark_targets<K>(v, u, w, need, hot);
+    return;
+  }
   // into_vis: the OR goes into `visited` itself; a target seen unvisited in
   // global memory goes straight to the OR, one seen in the LDS snapshot is
   // read again from global memory first
@@ -153,60 +183,6 @@ __device__ __forceinline__ void probe_batch(const View &v, const int32_t (&u)[K]
 #pragma unroll
   for (int j = 0; j < K; ++j)
     if (!((nx[j] >> (u[j] & 31)) & 1u)) atomic_or_noret32(tgt32 + ((uint32_t)u[j] >> 5), 1u << (u[j] & 31));
-}
-
-// Dense probes of one adjacency range of `deg` entries starting at `row`
-// (wave-uniform), K rows of 64 entries at a time. Addresses are a uniform
-// base plus 32-bit lane offsets, so a row costs few vector instructions: the
-// column load index is clamped (no per-lane branch around it), visited words
-// of hub targets come from the LDS copy and the rest from global memory into
-// separate registers, and only lanes whose target is unvisited read `next`
-// and OR into it.
-template <int K>
-__device__ __forceinline__ void dense_rows(const View &v, const int32_t *row, int32_t deg, HotCache hot) {
-  const int lane = lane_id();
-  const uint32_t *vis32 = reinterpret_cast<const uint32_t *>(v.visited);
-  uint32_t *next32 = reinterpret_cast<uint32_t *>(v.next);
-  uint32_t *tgt32 = v.into_vis ? reinterpret_cast<uint32_t *>(v.visited) : next32;
-  const lds_u32 *hot32 = (const lds_u32 *)(hot.lds);
-  const uint32_t hot_w32 = hot.words * 2;
-  for (int32_t r0 = 0; r0 < deg; r0 += kWave * K) {
-    int32_t u[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      // 32-bit byte offset from a scalar base (deg < 2^30)
-      const uint32_t off = (uint32_t)min(r0 + j * kWave + lane, deg - 1) << 2;
-      u[j] = __builtin_nontemporal_load(
-          reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(row) + off));
-    }
-    uint32_t lv[K], gv[K];
-    if (hot_w32) {
-#pragma unroll
-      for (int j = 0; j < K; ++j) lv[j] = hot32[min((uint32_t)u[j] >> 5, hot_w32 - 1)];
-    }
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      gv[j] = 0u;
-      if (((uint32_t)u[j] >> 5) >= hot_w32) gv[j] = vis32[(uint32_t)u[j] >> 5];
-    }
-    bool need[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const uint32_t w = (uint32_t)u[j] >> 5;
-      const uint32_t vis = w < hot_w32 ? lv[j] : gv[j];
-      need[j] = r0 + j * kWave + lane < deg && !((vis >> (u[j] & 31)) & 1u);
-    }
-    // into_vis: as in probe_batch
-    uint32_t nx[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      nx[j] = ~0u;
-      if (need[j]) nx[j] = (v.into_vis && ((uint32_t)u[j] >> 5) >= hot_w32) ? 0u : tgt32[(uint32_t)u[j] >> 5];
-    }
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-      if (!((nx[j] >> (u[j] & 31)) & 1u)) atomic_or_noret32(tgt32 + ((uint32_t)u[j] >> 5), 1u << (u[j] & 31));
-  }
 }
 
 // Per-lane totals of a queue-only level, reduced once per workgroup.
@@ -236,7 +212,7 @@ __device__ __forceinline__ void probe_batch_sparse(const View &v, const int32_t 
   }
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    int64_t deg = 0;
+    int64_t deg = 0, start = 0;
     int t = 0;
     bool own = false;
     if (win[j]) {
@@ -246,7 +222,8 @@ __device__ __forceinline__ void probe_batch_sparse(const View &v, const int32_t 
       own = x >= v.vb && x < v.ve;
       if (own) {
         const int64_t li = x - v.vb;
-        deg = v.rp[li + 1] - v.rp[li];
+        start = v.rp[li];
+        deg = v.rp[li + 1] - start;
         const int b = degree_bin(deg);
         t = tier_of_bin(b, v.small_bin, v.wave_bin);
         acc.owned += 1;
@@ -261,14 +238,20 @@ __device__ __forceinline__ void probe_batch_sparse(const View &v, const int32_t 
       uint32_t base = 0;
       if (lane == ld) base = atomic_add32(&v.ctl->qn[nxt][0], (uint32_t)__popcll(m0));
       base = __builtin_amdgcn_readlane(base, ld);
-      if (own && t == 0) v.q0[nxt][base + rank_below(m0)] = u[j];
+      if (own && t == 0) {
+        v.q0[nxt][base + rank_below(m0)] = u[j];
+        v.qr0[nxt][base + rank_below(m0)] = pack_row(start, deg);
+      }
     }
     if (m1) {
       const int ld = __ffsll((unsigned long long)m1) - 1;
       uint32_t base = 0;
       if (lane == ld) base = atomic_add32(&v.ctl->qn[nxt][1], (uint32_t)__popcll(m1));
       base = __builtin_amdgcn_readlane(base, ld);
-      if (own && t == 1) v.q1[nxt][base + rank_below(m1)] = u[j];
+      if (own && t == 1) {
+        v.q1[nxt][base + rank_below(m1)] = u[j];
+        v.qr1[nxt][base + rank_below(m1)] = pack_row(start, deg);
+      }
     }
     if (own && t == 2) {
       // one packed atomic per hub keeps slot order and chunk starts monotone
@@ -280,6 +263,171 @@ __device__ __forceinline__ void probe_batch_sparse(const View &v, const int32_t 
     }
   }
 }
+
+// ---------------------------------------------------------------------------
+// Row streams of the dense expansion. A wavefront walks its share of a tier
+// as a sequence of rows of up to 64 adjacency entries (one per lane; the
+// entry addresses of a row are a wave-uniform base plus the lane). Rows are
+// taken K at a time, and the column ids of the next K rows are requested
+// before the current K rows are probed, so each wavefront keeps one batch of
+// column loads in flight behind its probes.
+// ---------------------------------------------------------------------------
+
+template <int K>
+struct Rows {
+  int64_t base[K];  // wave-uniform
+  int32_t cnt[K];   // entries in the row (0: empty)
+};
+
+template <int K>
+__device__ __forceinline__ void load_rows(const View &v, const Rows<K> &r, int32_t (&u)[K]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    u[j] = 0;
+    if (lane < r.cnt[j]) u[j] = load_col(v.col, r.base[j] + lane);
+  }
+}
+
+template <int K, class Src>
+__device__ __forceinline__ void stream_rows(const View &v, Src &src, HotCache hot) {
+  const int lane = lane_id();
+  Rows<K> ra;
+  int32_t ua[K];
+  if (!src.fill(v, ra)) return;
+  load_rows<K>(v, ra, ua);
+  for (;;) {
+    Rows<K> rb;
+    int32_t ub[K];
+    const bool more = src.fill(v, rb);
+    if (more) load_rows<K>(v, rb, ub);
+    bool ok[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) ok[j] = lane < ra.cnt[j];
+    probe_batch<K>(v, ua, ok, hot);
+    if (!more) break;
+    ra = rb;
+#pragma unroll
+    for (int j = 0; j < K; ++j) ua[j] = ub[j];
+  }
+}
+
+// Tier-1 rows of one wavefront: its vertices are queue entries gwave +
+// k * nwaves (k < nmine); their packed rows are read 64 at a time (lane l
+// holds vertex wbase + l), the next 64 requested when a window is opened.
+struct WaveRows {
+  const uint64_t *q;
+  uint64_t gwave, nwaves;
+  uint32_t nmine, k, wbase;
+  uint64_t win, nwin;
+  int64_t pos, end;
+  uint64_t scanned;
+
+  __device__ __forceinline__ uint64_t window(uint32_t b) const {
+    const uint32_t kk = b + (uint32_t)lane_id();
+    return kk < nmine ? q[gwave + (uint64_t)kk * nwaves] : 0ull;
+  }
+  __device__ __forceinline__ void init(const uint64_t *queue, uint64_t gw, uint64_t nw, uint32_t mine) {
+    q = queue;
+    gwave = gw;
+    nwaves = nw;
+    nmine = mine;
+    k = 0;
+    wbase = 0;
+    win = window(0);
+    nwin = window(kWave);
+    pos = end = 0;
+    scanned = 0;
+  }
+  template <int K>
+  __device__ __forceinline__ bool fill(const View &, Rows<K> &r) {
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      while (pos >= end && k < nmine) {
+        if (k - wbase == (uint32_t)kWave) {
+          win = nwin;
+          wbase += kWave;
+          nwin = window(wbase + kWave);
+        }
+        const uint64_t pr = readlane64(win, (int)(k - wbase));
+        pos = (int64_t)(pr >> kRowShift);
+        end = pos + (int64_t)(pr & ((1ull << kRowShift) - 1));
+        scanned += (uint64_t)(end - pos);
+        ++k;
+      }
+      if (pos < end) {
+        r.base[j] = pos;
+        r.cnt[j] = (int32_t)min<int64_t>(kWave, end - pos);
+        pos += kWave;
+        any = true;
+      } else {
+        r.base[j] = 0;
+        r.cnt[j] = 0;
+      }
+    }
+    return any;
+  }
+};
+
+// Tier-2 rows of one wavefront: the chunks [c, c_hi) of the level's chunk
+// sequence (hub slot s holds chunks [cstart[s], cstart[s+1]); chunk i of a
+// hub covers its entries [i << chunk_shift, (i + 1) << chunk_shift)).
+struct HubRows {
+  int cur;
+  uint32_t n2, s;
+  uint64_t nch, c, c_hi;
+  int64_t pos, end;
+  uint64_t scanned;
+
+  // Opens slot s at chunk c: the entries of chunks [c, min(c_hi, next slot)).
+  __device__ __forceinline__ void open(const View &v) {
+    const uint64_t cs = v.cstart[cur][s];
+    const uint64_t cn = s + 1 < n2 ? (uint64_t)v.cstart[cur][s + 1] : nch;
+    const int64_t li = v.q2[cur][s] - v.vb;
+    const int64_t rb = v.rp[li], re = v.rp[li + 1];
+    const uint64_t stop = min(c_hi, cn);
+    pos = uniform64(rb + ((int64_t)(c - cs) << v.chunk_shift));
+    end = uniform64(min(re, rb + ((int64_t)(stop - cs) << v.chunk_shift)));
+    scanned += (uint64_t)(end - pos);
+    c = stop;
+  }
+  __device__ __forceinline__ void init(const View &v, int cur_, uint32_t n2_, uint64_t nch_, uint64_t c_lo,
+                                       uint64_t c_hi_) {
+    cur = cur_;
+    n2 = n2_;
+    nch = nch_;
+    c = c_lo;
+    c_hi = c_hi_;
+    pos = end = 0;
+    scanned = 0;
+    if (c < c_hi) {
+      s = wave_upper_slot(v.cstart[cur], n2, c);
+      open(v);
+    }
+  }
+  template <int K>
+  __device__ __forceinline__ bool fill(const View &v, Rows<K> &r) {
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      while (pos >= end && c < c_hi) {
+        ++s;
+        open(v);
+      }
+      if (pos < end) {
+        r.base[j] = pos;
+        r.cnt[j] = (int32_t)min<int64_t>(kWave, end - pos);
+        pos += kWave;
+        any = true;
+      } else {
+        r.base[j] = 0;
+        r.cnt[j] = 0;
+      }
+    }
+    return any;
+  }
+};
 
 constexpr int kUnroll = 4;       // edges per lane in flight (wavefront / workgroup tiers)
 constexpr int kUnrollSmall = 8;  // edges per lane in flight (lane-group tier)
@@ -318,74 +466,87 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     v.ctl->ownedcnt[(level + 1) % 3] = 0;
   }
 
-  // Tier 2: heavy vertices cut into fixed-size edge chunks, one wavefront per
-  // chunk; the wavefront finds the chunk's vertex with a 64-way search of the
-  // chunk starts.
+  // Tier 2: heavy vertices cut into fixed-size edge chunks. A dense level
+  // gives each wavefront a contiguous range of chunks and streams its rows
+  // (a hub spans the ranges of several wavefronts, and a wavefront's range
+  // crosses few hubs); a queue-only level takes one chunk at a time and finds
+  // the chunk's vertex with a 64-way search of the chunk starts.
   const uint64_t hv = load_relaxed64(&v.ctl->heavy[cur]);
   const uint32_t n2 = (uint32_t)(hv >> kHeavyShift);
   const uint64_t nch = hv & kChunkMask;
-  for (uint64_t c = gwave; c < nch; c += nwaves) {
-    const uint32_t s = wave_upper_slot(v.cstart[cur], n2, c);
-    const int64_t li = v.q2[cur][s] - v.vb;
-    const int64_t b = v.rp[li], e = v.rp[li + 1];
-    const int64_t lo = b + ((int64_t)(c - v.cstart[cur][s]) << v.chunk_shift);
-    const int64_t hi = min(e, lo + (1ll << v.chunk_shift));
-    scanned += (uint64_t)(hi - lo);
-    if (!SPARSE) {
-      const int64_t ulo = uniform64(lo);
-      dense_rows<KU>(v, v.col + ulo, (int32_t)(uniform64(hi) - ulo), hot);
-      continue;
+  if (!SPARSE) {
+    if (nch) {
+      HubRows src;
+      src.init(v, cur, n2, nch, gwave * nch / nwaves, (gwave + 1) * nch / nwaves);
+      stream_rows<KU>(v, src, hot);
+      scanned += src.scanned;
     }
-    for (int64_t e0 = lo; e0 < hi; e0 += kWave * KU) {
-      int32_t u[KU];
-      bool ok[KU];
+  } else {
+    for (uint64_t c = gwave; c < nch; c += nwaves) {
+      const uint32_t s = wave_upper_slot(v.cstart[cur], n2, c);
+      const int64_t li = v.q2[cur][s] - v.vb;
+      const int64_t b = v.rp[li], e = v.rp[li + 1];
+      const int64_t lo = b + ((int64_t)(c - v.cstart[cur][s]) << v.chunk_shift);
+      const int64_t hi = min(e, lo + (1ll << v.chunk_shift));
+      scanned += (uint64_t)(hi - lo);
+      for (int64_t e0 = lo; e0 < hi; e0 += kWave * KU) {
+        int32_t u[KU];
+        bool ok[KU];
 #pragma unroll
-      for (int j = 0; j < KU; ++j) {
-        const int64_t k = e0 + (int64_t)j * kWave + lane;
-        ok[j] = k < hi;
-        u[j] = ok[j] ? load_col(v.col, k) : 0;
+        for (int j = 0; j < KU; ++j) {
+          const int64_t k = e0 + (int64_t)j * kWave + lane;
+          ok[j] = k < hi;
+          u[j] = ok[j] ? load_col(v.col, k) : 0;
+        }
+        probe_dispatch<SPARSE, KU>(v, u, ok, level, acc, hot, dist);
       }
-      probe_dispatch<SPARSE, KU>(v, u, ok, level, acc, hot, dist);
     }
   }
 
-  // Tier 1: one wavefront per vertex.
+  // Tier 1: one wavefront per vertex (vertex i of the queue to wavefront
+  // i mod nwaves). A dense level streams the wavefront's vertices as one
+  // sequence of 64-entry rows, their packed rows read 64 vertices at a time.
   const uint32_t n1 = load_relaxed32(&v.ctl->qn[cur][1]);
-  for (uint64_t i = gwave; i < n1; i += nwaves) {
-    const int64_t li = v.q1[cur][i] - v.vb;
-    const int64_t b = v.rp[li], e = v.rp[li + 1];
-    scanned += (uint64_t)(e - b);
-    if (!SPARSE) {
-      const int64_t ub = uniform64(b);
-      dense_rows<KU>(v, v.col + ub, (int32_t)(uniform64(e) - ub), hot);
-      continue;
+  if (!SPARSE) {
+    if (n1 > gwave) {
+      WaveRows src;
+      src.init(v.qr1[cur], gwave, nwaves, (uint32_t)((n1 - gwave + nwaves - 1) / nwaves));
+      stream_rows<KU>(v, src, hot);
+      scanned += src.scanned;
     }
-    for (int64_t k0 = b; k0 < e; k0 += kWave * KU) {
-      int32_t u[KU];
-      bool ok[KU];
+  } else {
+    for (uint64_t i = gwave; i < n1; i += nwaves) {
+      const uint64_t pr = v.qr1[cur][i];
+      const int64_t b = (int64_t)(pr >> kRowShift), e = b + (int64_t)(pr & ((1ull << kRowShift) - 1));
+      scanned += (uint64_t)(e - b);
+      for (int64_t k0 = b; k0 < e; k0 += kWave * KU) {
+        int32_t u[KU];
+        bool ok[KU];
 #pragma unroll
-      for (int j = 0; j < KU; ++j) {
-        const int64_t k = k0 + (int64_t)j * kWave + lane;
-        ok[j] = k < e;
-        u[j] = ok[j] ? load_col(v.col, k) : 0;
+        for (int j = 0; j < KU; ++j) {
+          const int64_t k = k0 + (int64_t)j * kWave + lane;
+          ok[j] = k < e;
+          u[j] = ok[j] ? load_col(v.col, k) : 0;
+        }
+        probe_dispatch<SPARSE, KU>(v, u, ok, level, acc, hot, dist);
       }
-      probe_dispatch<SPARSE, KU>(v, u, ok, level, acc, hot, dist);
     }
   }
 
   // Tier 0: 64 vertices per wavefront, their edges dealt evenly to the lanes.
   // Tier-0 degrees are below 2^23 (small_bin <= 24), so the wavefront's edge
   // prefix sums fit in 32 bits and each search step is one 32-bit shuffle.
+  // The packed rows of the wavefront's next group are requested before the
+  // current group is expanded.
   const uint32_t n0 = load_relaxed32(&v.ctl->qn[cur][0]);
-  for (uint64_t base = gwave * kWave; base < n0; base += nwaves * kWave) {
-    const uint64_t i = base + lane;
-    int64_t start = 0;
-    int32_t deg = 0;
-    if (i < n0) {
-      const int64_t li = v.q0[cur][i] - v.vb;
-      start = v.rp[li];
-      deg = (int32_t)(v.rp[li + 1] - start);
-    }
+  uint64_t base = gwave * kWave;
+  uint64_t pr_cur = base + lane < n0 ? v.qr0[cur][base + lane] : 0ull;
+  for (; base < n0; base += nwaves * kWave) {
+    const uint64_t nb = base + nwaves * kWave;
+    const uint64_t pr_next = nb + lane < n0 ? v.qr0[cur][nb + lane] : 0ull;
+    const int64_t start = (int64_t)(pr_cur >> kRowShift);
+    const int32_t deg = (int32_t)(pr_cur & ((1ull << kRowShift) - 1));
+    pr_cur = pr_next;
     const int32_t incl = wave_incl_scan32(deg);
     const int32_t total = __shfl(incl, kWave - 1);
     // edge e of the batch is edge (e - excl[k]) of lane k's vertex, k the first
@@ -416,6 +577,14 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     // scanned, one atomic per workgroup, and the frontier size.
     if (lane == 0) s_acc[0][wave] = scanned;
     __syncthreads();
+    if (v.hubnext && hot.words) {
+      // hub targets this block found: LDS copy bits not set in `visited`
+      // (which no expansion changes in mark mode)
+      for (uint32_t i = threadIdx.x; i < hot.words; i += BLOCK) {
+        const uint64_t f = hot.lds[i] & ~v.visited[i];
+        if (f) atomic_or_noret(v.hubnext + i, f);
+      }
+    }
     if (threadIdx.x == 0) {
       uint64_t t = 0;
       for (int w = 0; w < kWaves; ++w) t += s_acc[0][w];
@@ -465,6 +634,11 @@ __device__ __forceinline__ uint64_t owned_mask(int64_t w, int64_t vb, int64_t ve
   return m;
 }
 
+// Four mark bytes (each 0 or 1) of a little-endian dword -> four bits.
+__device__ __forceinline__ uint32_t marks_to_bits(uint32_t x) {
+  return (x & 1u) | ((x >> 7) & 2u) | ((x >> 14) & 4u) | ((x >> 21) & 8u);
+}
+
 // MODE is a kMerge* constant (the ordinary merge compiles without the other
 // modes' branches).
 template <int MODE>
@@ -501,6 +675,35 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
         nw = v.front[w] & tail;
         om = nw & owned_mask(w, v.vb, v.ve);
       }
+    } else if (w < v.words && v.mark) {
+      // byte marks of the word's 64 vertices (set only for vertices that
+      // were unvisited): fold them into a bit mask and clear them
+      uint4 *mp = reinterpret_cast<uint4 *>(v.mark + (size_t)w * 64);
+      uint4 q[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q[k] = mp[k];
+      uint64_t mk = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        mk |= (uint64_t)(marks_to_bits(q[k].x) | (marks_to_bits(q[k].y) << 4) |
+                         (marks_to_bits(q[k].z) << 8) | (marks_to_bits(q[k].w) << 12))
+              << (16 * k);
+      if (w < v.hub_words) {
+        const uint64_t h = v.hubnext[w];
+        if (h) {
+          v.hubnext[w] = 0ull;
+          mk |= h;
+        }
+      }
+      if (mk) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (q[k].x | q[k].y | q[k].z | q[k].w) mp[k] = make_uint4(0u, 0u, 0u, 0u);
+        const uint64_t vis = v.visited[w];
+        nw = mk & ~vis;
+        if (nw) v.visited[w] = vis | nw;
+      }
+      om = nw & owned_mask(w, v.vb, v.ve);
     } else if (w < v.words && v.into_vis) {
       // the expansion ORed into `visited`; `next` holds visited as it was at
       // the level's start, and becomes the current visited
@@ -670,36 +873,61 @@ __device__ __forceinline__ void merge_phase(const View &v, int32_t *dist, const 
       cb += s_chunks[x];
     }
 
-    // Pass 2: write owned new vertices into the level L+1 tier queues.
+    // Pass 2: write owned new vertices into the level L+1 tier queues, with
+    // the packed rows of tier-0/1 entries. Words are taken eight at a time so
+    // their row-offset loads (cache hits after pass 1) are in flight together.
     act = ballot(om != 0);
     while (act) {
-      const int j = __ffsll((unsigned long long)act) - 1;
-      act &= act - 1;
-      const uint64_t oj = readlane64(om, j);
-      const uint64_t m1 = readlane64(t1m, j);
-      const uint64_t m2 = readlane64(t2m, j);
-      const uint64_t m0 = oj & ~m1 & ~m2;
-      const int32_t vtx = (int32_t)((wbase + j) * 64 + lane);
-      if ((m0 >> lane) & 1ull) v.q0[nxt][b0 + rank_below(m0)] = vtx;
-      if ((m1 >> lane) & 1ull) v.q1[nxt][b1 + rank_below(m1)] = vtx;
-      b0 += (uint32_t)__popcll(m0);
-      b1 += (uint32_t)__popcll(m1);
-      if (m2) {
-        const bool mine = (m2 >> lane) & 1ull;
-        int64_t nc = 0;
-        if (mine) {
-          const int64_t li = vtx - v.vb;
-          const int64_t deg = v.rp[li + 1] - v.rp[li];
-          nc = (deg + (1ll << cs) - 1) >> cs;
+      constexpr int kW = 8;
+      int js[kW];
+      int cnt = 0;
+#pragma unroll
+      for (int q = 0; q < kW; ++q) {
+        js[q] = act ? __ffsll((unsigned long long)act) - 1 : 0;
+        if (act) { act &= act - 1; ++cnt; }
+      }
+      int64_t r0[kW], r1[kW];
+#pragma unroll
+      for (int q = 0; q < kW; ++q) {
+        r0[q] = r1[q] = 0;
+        const uint64_t oj = q < cnt ? readlane64(om, js[q]) : 0ull;
+        if ((oj >> lane) & 1ull) {
+          const int64_t li = (wbase + js[q]) * 64 + lane - v.vb;
+          r0[q] = v.rp[li];
+          r1[q] = v.rp[li + 1];
         }
-        const int64_t incl = wave_incl_scan(nc);
-        if (mine) {
-          const uint32_t slot = b2 + rank_below(m2);
-          v.q2[nxt][slot] = vtx;
-          v.cstart[nxt][slot] = (uint32_t)(cb + (uint64_t)(incl - nc));
+      }
+#pragma unroll
+      for (int q = 0; q < kW; ++q) {
+        if (q >= cnt) break;
+        const int j = js[q];
+        const uint64_t oj = readlane64(om, j);
+        const uint64_t m1 = readlane64(t1m, j);
+        const uint64_t m2 = readlane64(t2m, j);
+        const uint64_t m0 = oj & ~m1 & ~m2;
+        const int32_t vtx = (int32_t)((wbase + j) * 64 + lane);
+        const int64_t deg = r1[q] - r0[q];
+        if ((m0 >> lane) & 1ull) {
+          v.q0[nxt][b0 + rank_below(m0)] = vtx;
+          v.qr0[nxt][b0 + rank_below(m0)] = pack_row(r0[q], deg);
+        } else if ((m1 >> lane) & 1ull) {
+          v.q1[nxt][b1 + rank_below(m1)] = vtx;
+          v.qr1[nxt][b1 + rank_below(m1)] = pack_row(r0[q], deg);
         }
-        b2 += (uint32_t)__popcll(m2);
-        cb += (uint64_t)shfl64(incl, kWave - 1);
+        b0 += (uint32_t)__popcll(m0);
+        b1 += (uint32_t)__popcll(m1);
+        if (m2) {
+          const bool mine = (m2 >> lane) & 1ull;
+          const int64_t nc = mine ? (deg + (1ll << cs) - 1) >> cs : 0;
+          const int64_t incl = wave_incl_scan(nc);
+          if (mine) {
+            const uint32_t slot = b2 + rank_below(m2);
+            v.q2[nxt][slot] = vtx;
+            v.cstart[nxt][slot] = (uint32_t)(cb + (uint64_t)(incl - nc));
+          }
+          b2 += (uint32_t)__popcll(m2);
+          cb += (uint64_t)shfl64(incl, kWave - 1);
+        }
       }
     }
     __syncthreads();  // s_cnt / s_base reuse

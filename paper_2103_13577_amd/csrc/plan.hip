@@ -143,6 +143,7 @@ bfs_status choose_tuning(Plan *p) {
     if (p->opt.hot_words > 0) t.hot_words = p->opt.hot_words;
     if (p->opt.sparse_div > 0) t.sparse_div = p->opt.sparse_div;
     if (p->opt.sparse_div < 0) t.sparse_div = 0;
+    if (p->opt.mark_mode < 0) t.mark = 0;
     // the kernels' static LDS needs under 1 KB next to the hub copy
     if ((int64_t)t.hot_words * 8 + 1024 > p->max_lds)
       return p->fail(BFS_ERR_ARG, "hot_words exceeds the LDS one workgroup may use");

@@ -23,7 +23,10 @@ namespace bfsk {
 struct WsLayout {
   size_t ctl, lvl_frontier, lvl_hist, visited, next, front;
   size_t list_blk;  // uint64[kListMaxBlocks + 1]: block counts of the list export
+  size_t mark = 0;  // uint8[64 * words]: per-vertex marks of dense levels (whole graphs; 0: none)
+  size_t hubnext = 0;  // uint64[kMaxHotWords]: hub targets found by a level (follows mark)
   size_t q[3][kRing];
+  size_t qr[2][kRing];  // uint64[omax]: packed rows of the tier-0/1 queues
   size_t cstart[kRing];
   // batched multi-source state (see msbfs_core.hpp)
   // relabelled copies (per graph; 0 when the graph is not relabelled) and
@@ -50,6 +53,7 @@ struct Tuning {
   int32_t loop_mode = 0;        // chosen level loop (BFS_LOOP_HOST or BFS_LOOP_PERSISTENT)
   float tuned_ms = 0.f;         // best time seen by the autotuner
   int32_t hot_words = 0;        // visited words kept in LDS by each expansion block (0: off)
+  int32_t mark = 1;             // single-node dense levels: byte marks (1) or atomic ORs (0)
 };
 
 struct BatchState;  // batched / serving state (msbfs.hip)
@@ -78,6 +82,8 @@ struct bfs_plan_s {
   static constexpr int kTimedLevels = 64;
   hipEvent_t lev[kTimedLevels][3] = {};  // per level: before expand, after expand, after merge
   bool time_levels = false;              // set while bfs_run drives the host loop
+  float lev_ms[kTimedLevels][2] = {};    // last host-driven traversal: Phase 1 / Phase 2 ms per level
+  int32_t timed_levels = 0;              // levels in lev_ms (0: the last traversal was not host-driven)
   std::string err;
 
   // single-source traversal state
@@ -104,6 +110,8 @@ struct bfs_plan_s {
   bool cur_do = false;                // the running traversal may go bottom-up
   bool cur_front = false;             // merges write the next level's frontier bitmap
   bool cur_into_vis = false;          // dense expansions OR into `visited` (see View::into_vis)
+  bool cur_mark = false;              // dense expansions set byte marks (see View::mark)
+  bool marks_clean = false;           // every mark byte is 0 (a finished traversal clears its marks)
   bool bu_state = false;              // the current level runs bottom-up
   int front_level = -1;               // level whose frontier the front bitmap holds
   int32_t merge_mode = 0;             // mode of bfs_merge_frontier's merge (bfs_run's bottom-up levels)
@@ -153,6 +161,7 @@ void layout_relabel(const bfs_graph *g, int32_t ng, const bfs_options *o, WsLayo
 bool relabel_wanted(const bfs_graph &g, const bfs_options *o);
 bfs_status relabel_graphs(Plan *p);
 bfs_status autotune_graphs(Plan *p);
+bfs_status prepare_run_loops(Plan *p);
 void layout_batch(const bfs_graph *g, int32_t ng, const bfs_options *o, WsLayout &L, size_t &off);
 bfs_status validate_graphs(Plan *p);
 bfs_status choose_tuning(Plan *p);

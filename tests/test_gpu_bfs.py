@@ -65,13 +65,18 @@ MODES = [dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST),
          dict(direction=pkg.DIR_OPTIMIZING),
          dict(direction=pkg.DIR_OPTIMIZING, sparse_div=-1, relabel=-1),
          dict(loop_mode=pkg.LOOP_GRAPH, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64),
-         # every level dense in the host-driven loop: the expansions OR into
-         # the visited bitmap itself (narrow and wide expansion, both tiers)
+         # every level dense (no queue-only level): the expansions set byte
+         # marks, hub targets stay in the LDS copy (narrow and wide expansion)
          dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1, hot_words=16384, small_bin=3, wave_bin=6,
               chunk_edges=128),
          dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1, relabel=-1, small_bin=2, wave_bin=4, chunk_edges=64),
          dict(loop_mode=pkg.LOOP_GRAPH, sparse_div=-1, hot_words=16384),
-         dict(loop_mode=pkg.LOOP_PERSISTENT, sparse_div=-1, small_bin=2, wave_bin=4, chunk_edges=64)]
+         dict(loop_mode=pkg.LOOP_PERSISTENT, sparse_div=-1, small_bin=2, wave_bin=4, chunk_edges=64),
+         # the same all-dense loops with the atomic-OR expansion instead of byte marks
+         dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1, hot_words=16384, small_bin=3, wave_bin=6,
+              chunk_edges=128, mark_mode=-1),
+         dict(loop_mode=pkg.LOOP_GRAPH, sparse_div=-1, hot_words=2048, mark_mode=-1),
+         dict(loop_mode=pkg.LOOP_PERSISTENT, sparse_div=-1, mark_mode=-1)]
 
 
 @pytest.mark.parametrize("name,make,sources", SMALL_GRAPHS, ids=[x[0] for x in SMALL_GRAPHS])
@@ -730,25 +735,81 @@ def test_error_paths(gpu):
     plan.close()
 
 
-@pytest.mark.parametrize("scale", [24])
-def test_full_size_rmat24_ef16(gpu, scale):
-    """The benchmark's workload (R-MAT scale 24, edge factor 16) in the
-    benchmark's launch configuration: full bit-exact distance arrays for two
-    seeded sources and the canonical parents of one."""
-    import torch
+@pytest.fixture(scope="module")
+def rmat24(gpu):
+    """The benchmark's graph: R-MAT scale 24, edge factor 16, its seeds, on
+    the device, with the oracle's distances cached per source."""
+    import bench
     print("[gpu] generating rmat24", flush=True)
-    g = gg.rmat(scale, 16, seed=0x5EED0024, perm_seed=0xBEEF0024)
+    gseed, pseed, _ = bench.SEEDS["rmat24"]
+    g = gg.rmat(24, 16, seed=gseed, perm_seed=pseed)
     dg = pkg.DeviceGraph.from_csr(g, gpu)
-    plan = pkg.Plan([dg])
-    for i, s in enumerate(gg.pick_sources(g, 2, seed=0xC0FFEE24)):
-        print(f"[gpu] rmat24 src={s}", flush=True)
+    refs = {}
+
+    def ref(s):
+        if s not in refs:
+            refs[s] = oracle.bfs(g, s)
+        return refs[s]
+    yield g, dg, ref
+    del dg
+
+
+def test_headline_plan_rmat24(gpu, rmat24):
+    """Exactly what the benchmark times: its pinned headline plan (host-driven
+    loop, the 1024-thread expansion with a 16K-word LDS hub copy against a
+    262,144-word bitmap, every level dense, byte marks) on its graph, from two
+    of its timed sources (indices 3 and 4 of its seeded source sequence, timed
+    under the default warm-up of 3): whole distance arrays bit-exact against
+    the oracle, and the canonical parents of one source."""
+    import torch
+    import bench
+    g, dg, ref = rmat24
+    plan = pkg.Plan([dg], **bench.HEADLINE_PLAN)
+    t = plan.tuning(0)
+    assert t["loop_mode"] == pkg.LOOP_HOST and t["relabelled"] == 1
+    assert 4096 < t["hot_words"] < (g.n + 63) // 64  # wide expansion; copy smaller than the bitmap
+    assert t["sparse_div"] == 0 and t["mark_mode"] == 1
+    srcs = bench.headline_sources(g, 5)[3:5]
+    for i, s in enumerate(srcs):
+        print(f"[gpu] rmat24 headline plan src={s}", flush=True)
         d, p, st = plan.run(0, int(s), parent=(i == 0))
         torch.cuda.synchronize()
-        ref = oracle.bfs(g, int(s))
-        assert np.array_equal(d.cpu().numpy(), ref)
+        r = ref(int(s))
+        assert np.array_equal(d.cpu().numpy(), r)
         if i == 0:
-            assert np.array_equal(p.cpu().numpy(), oracle.parent(g, ref))
-        assert st.edges_scanned == oracle.edges_scanned(g, ref)
+            assert np.array_equal(p.cpu().numpy(), oracle.parent(g, r))
+        assert st.edges_scanned == oracle.edges_scanned(g, r)
+        assert st.expand_launches == st.levels  # every level ran the dense expansion
+        assert st.dense_edges == st.edges_scanned
+    plan.close()
+
+
+FULL_SIZE_PLANS = [dict(loop_mode=pkg.LOOP_HOST, autotune=-1),
+                   dict(loop_mode=pkg.LOOP_GRAPH, autotune=-1),
+                   dict(loop_mode=pkg.LOOP_PERSISTENT, autotune=-1),
+                   dict(loop_mode=pkg.LOOP_GRAPH, autotune=-1, sparse_div=-1, hot_words=16384),
+                   dict(loop_mode=pkg.LOOP_HOST, autotune=-1, sparse_div=-1, hot_words=16384,
+                        small_bin=8, wave_bin=15, chunk_edges=1024, mark_mode=-1)]
+
+
+@pytest.mark.parametrize("plan_opts", FULL_SIZE_PLANS, ids=[str(i) for i in range(len(FULL_SIZE_PLANS))])
+def test_full_size_rmat24_ef16(gpu, rmat24, plan_opts):
+    """The benchmark's workload under explicit plans (no autotuning, so the
+    kernels covered do not depend on timing): host-driven, captured-graph
+    and cooperative loops, all-dense levels with byte marks in the captured
+    loop, and the atomic-OR expansion. Whole distance arrays bit-exact
+    against the oracle for one of the benchmark's sources."""
+    import torch
+    import bench
+    g, dg, ref = rmat24
+    plan = pkg.Plan([dg], **plan_opts)
+    s = int(bench.headline_sources(g, 1)[0])
+    print(f"[gpu] rmat24 src={s} plan={plan_opts}", flush=True)
+    d, _, st = plan.run(0, s)
+    torch.cuda.synchronize()
+    r = ref(s)
+    assert np.array_equal(d.cpu().numpy(), r)
+    assert st.edges_scanned == oracle.edges_scanned(g, r)
     plan.close()
 
 
@@ -772,3 +833,41 @@ def test_graph_replays_match_eager(gpu):
         assert st.levels == int(ref.max()) + 1
     pg.close()
     ph.close()
+
+
+NO_ALLOC_PLANS = [dict(loop_mode=pkg.LOOP_HOST), dict(loop_mode=pkg.LOOP_GRAPH),
+                  dict(loop_mode=pkg.LOOP_GRAPH, sparse_div=-1, hot_words=2048),
+                  dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1),
+                  dict(loop_mode=pkg.LOOP_CU), dict()]
+
+
+@pytest.mark.parametrize("plan_opts", NO_ALLOC_PLANS, ids=[str(i) for i in range(len(NO_ALLOC_PLANS))])
+def test_run_allocates_nothing(gpu, plan_opts):
+    """Every buffer is sized at plan creation (Section 3, fixed preallocated
+    buffers): device free memory is the same before and after traversals in
+    every level loop. The captured level graph is instantiated at plan
+    creation, so even the first traversal of that loop allocates nothing;
+    other loops get one warm-up traversal first (the HIP runtime may set up a
+    kernel's private-memory backing on that kernel's first launch). The
+    workspace size depends on the graphs and options only."""
+    import torch
+    g = gg.rmat(15, 8, seed=91, perm_seed=92)
+    dg = pkg.DeviceGraph.from_csr(g, gpu)
+    plan = pkg.Plan([dg], **plan_opts)
+    plan2 = pkg.Plan([dg], **plan_opts)
+    assert plan.workspace_bytes == plan2.workspace_bytes
+    plan2.close()
+    dist = torch.empty(g.n, dtype=torch.int32, device=gpu)
+    srcs = [int(s) for s in gg.pick_sources(g, 5, seed=93)]
+    torch.cuda.synchronize()
+    if plan.tuning(0)["loop_mode"] != pkg.LOOP_GRAPH:
+        plan.run(0, srcs[0], dist=dist)
+        torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    for s in srcs[1:]:
+        plan.run(0, s, dist=dist)
+        torch.cuda.synchronize()
+        assert np.array_equal(dist.cpu().numpy(), oracle.bfs(g, s))
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 == free0, (free0, free1, plan.tuning(0))
+    plan.close()
