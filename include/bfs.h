@@ -337,6 +337,31 @@ bfs_status bfs_level_stats(bfs_plan_t p, int64_t *frontier, int64_t *hist, int32
 bfs_status bfs_level_times(bfs_plan_t p, float *expand_ms, float *merge_ms, int32_t *kind,
                            int32_t max_levels, int32_t *levels);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): a
+ * single-source traversal of a small whole graph that allocates nothing --
+ * no plan, no workspace. It runs the one-workgroup level loop of bfs_run
+ * (BFS_LOOP_CU, caller ids, no relabelled copy) with its device scratch (the
+ * control block and two frontier queues, BFS_NOALLOC_SCRATCH_BYTES in all)
+ * in a fixed device array of the library, one per GPU, held until the
+ * process ends. Every call on one GPU shares that array: calls that overlap
+ * on a GPU (other streams, other threads) race and must be serialised by the
+ * caller. g: host descriptor of a whole graph (v_begin 0, v_end n_global)
+ * with at most BFS_NOALLOC_MAX_VERTICES vertices and fewer than
+ * BFS_NOALLOC_MAX_EDGES edges, else BFS_ERR_CAPACITY; its device arrays are
+ * validated on every call (BFS_ERR_ARG when invalid). dist: device
+ * int32[n_global], written as by bfs_run. hip_stream: hipStream_t (NULL =
+ * null stream); the call returns after the traversal has finished. levels
+ * (host, may be NULL) receives the number of nonempty levels. Errors are
+ * described by bfs_last_error(NULL) on the calling thread.
+ */
+#define BFS_NOALLOC_MAX_VERTICES (1 << 19)
+#define BFS_NOALLOC_MAX_EDGES (1 << 25)
+#define BFS_NOALLOC_SCRATCH_BYTES (8 * BFS_NOALLOC_MAX_VERTICES + 16384)
+bfs_status bfs_run_noalloc(const bfs_graph *g, int64_t source, int32_t *dist, void *hip_stream,
+                           int32_t *levels);
+
 /* ------------------------------------------------------------------------ */
 /* Batched multi-source traversal and serving                               */
 /* ------------------------------------------------------------------------ */

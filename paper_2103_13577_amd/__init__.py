@@ -108,6 +108,7 @@ def lib():
         "bfs_finish": (i32, [vp, vp, ctypes.POINTER(bfs_stats)]),
         "bfs_level_stats": (i32, [vp, vp, vp, i32, ctypes.POINTER(i32)]),
         "bfs_level_times": (i32, [vp, vp, vp, vp, i32, ctypes.POINTER(i32)]),
+        "bfs_run_noalloc": (i32, [ctypes.POINTER(bfs_graph), i64, vp, vp, ctypes.POINTER(i32)]),
         "bfs_plan_tuning": (i32, [vp, i32, ctypes.POINTER(bfs_tuning)]),
         "bfs_batch_submit": (i32, [vp, ctypes.POINTER(bfs_query), i32, u32, ctypes.POINTER(u64)]),
         "bfs_batch_wait": (i32, [vp, u64, i64, ctypes.POINTER(bfs_batch_result)]),
@@ -132,7 +133,27 @@ EXPORTED = ("bfs_options_default", "bfs_workspace_size", "bfs_plan_create", "bfs
             "bfs_last_error", "bfs_run", "bfs_begin", "bfs_expand", "bfs_merge_frontier",
             "bfs_finish", "bfs_level_stats", "bfs_level_times", "bfs_plan_tuning", "bfs_batch_submit",
             "bfs_batch_wait", "bfs_batch_times", "bfs_batch_poll", "bfs_batch_tuning",
-            "bfs_frontier_list", "bfs_merge_lists", "bfs_expand_bottom_up")
+            "bfs_frontier_list", "bfs_merge_lists", "bfs_expand_bottom_up", "bfs_run_noalloc")
+
+NOALLOC_MAX_VERTICES = 1 << 19
+NOALLOC_MAX_EDGES = 1 << 25
+
+
+def run_noalloc(graph: "DeviceGraph", source: int, dist=None, stream=None):
+    """bfs_run_noalloc: one traversal of a small whole graph with the
+    library's fixed device scratch (no plan, no workspace). Returns
+    (dist, levels)."""
+    torch = _torch()
+    if dist is None:
+        dist = torch.empty(graph.n_global, dtype=torch.int32, device=graph.row_ptr.device)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    g = graph.c_struct()
+    lv = ctypes.c_int32(0)
+    st = lib().bfs_run_noalloc(ctypes.byref(g), int(source), dist.data_ptr(), s.cuda_stream,
+                               ctypes.byref(lv))
+    if st != BFS_OK:
+        raise BfsError(st, lib().bfs_last_error(None).decode())
+    return dist, int(lv.value)
 
 
 class BfsError(RuntimeError):

@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbfs.so")
-SOURCES = ["bfs_kernels.hip", "bfs_cu.hip", "frontier_list.hip", "bfs_capi.hip", "plan.hip", "msbfs.hip", "msbfs_kernels.hip", "relabel.hip", "autotune.hip"]
+SOURCES = ["bfs_kernels.hip", "bfs_cu.hip", "frontier_list.hip", "bfs_capi.hip", "plan.hip", "msbfs.hip", "msbfs_kernels.hip", "relabel.hip", "autotune.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -26,6 +26,10 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
 
+namespace bfsk {
+void set_create_error(const std::string &msg) { g_create_error = msg; }
+}  // namespace bfsk
+
 bfs_status bfs_plan_s::fail(bfs_status st, const std::string &msg) {
   err = msg;
   return st;

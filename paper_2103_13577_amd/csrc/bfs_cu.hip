@@ -43,6 +43,8 @@ __device__ __forceinline__ void lds_or(uint64_t *p, uint64_t bit) {
 // k_reset.
 __global__ void __launch_bounds__(kCuBlock) k_bfs_cu(View v, int64_t src_caller, int max_levels) {
   extern __shared__ uint64_t lds[];
+  // an error flagged before the launch (an invalid graph) skips the traversal
+  if (load_relaxed_i32(&v.ctl->err)) return;
   const int64_t W = v.words;
   uint64_t *vis = lds, *nxt = lds + W;
   __shared__ uint32_t s_qn[2];

@@ -162,6 +162,8 @@ bool relabel_wanted(const bfs_graph &g, const bfs_options *o);
 bfs_status relabel_graphs(Plan *p);
 bfs_status autotune_graphs(Plan *p);
 bfs_status prepare_run_loops(Plan *p);
+// Message that bfs_last_error(NULL) returns on this thread.
+void set_create_error(const std::string &msg);
 void layout_batch(const bfs_graph *g, int32_t ng, const bfs_options *o, WsLayout &L, size_t &off);
 bfs_status validate_graphs(Plan *p);
 bfs_status choose_tuning(Plan *p);
