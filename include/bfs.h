@@ -134,6 +134,17 @@ typedef struct {
                               byte per other candidate with a plain store; the merge folds
                               both into the visited bitmap. -1 = the expansion ORs bits into
                               the visited bitmap with device-scope atomics */
+  int64_t mem_budget_bytes; /* batched / streaming queries: admission bound on the memory of
+                              the queries in flight at once (0 = slots only). A query counts
+                              bfs_batch_query_bytes(): its distance output plus its share of
+                              the lane words (3 arrays x 8 bytes per 64 sources per vertex);
+                              it waits until the queries in flight leave room, and one that
+                              can never fit is refused at submission (BFS_ERR_CAPACITY) */
+  const char *tune_cache;  /* host path of a text file of tuned settings, or NULL. A plan whose
+                              graph, device and options match an entry takes its settings
+                              and skips the autotuner's timing runs; otherwise it autotunes
+                              and appends an entry. Lines are independent (a concurrent
+                              writer may add a duplicate entry, never a corrupt one) */
 } bfs_options;
 
 #define BFS_DIR_TOPDOWN 0
@@ -391,8 +402,12 @@ typedef struct {
  * as one multi-source bitset traversal per graph (64 sources per uint64 lane
  * word) and *ticket identifies it. With BFS_BATCH_STREAMING the queries join
  * the plan's serving loop: they are admitted into free lanes when lane memory
- * frees up and finish independently; *ticket identifies the group.
- * Requires batch_lanes > 0 at plan creation.
+ * frees up (and, with mem_budget_bytes > 0, when the queries in flight leave
+ * room for their admission cost) and finish independently; *ticket
+ * identifies the group. Requires batch_lanes > 0 at plan creation
+ * (BFS_ERR_CAPACITY otherwise). A query whose admission cost alone exceeds
+ * mem_budget_bytes can never be admitted: the call returns BFS_ERR_CAPACITY
+ * and submits none of the nq queries.
  */
 bfs_status bfs_batch_submit(bfs_plan_t p, const bfs_query *q, int32_t nq, uint32_t flags,
                             uint64_t *ticket);
@@ -416,6 +431,27 @@ bfs_status bfs_batch_poll(bfs_plan_t p, uint64_t *done, int32_t max, int32_t *n,
 /* Per-query completion times (host steady-clock ns) of a finished streaming
  * ticket, in submission order. */
 bfs_status bfs_batch_times(bfs_plan_t p, uint64_t ticket, int64_t *complete_ns, int32_t nq);
+
+/*
+ * Admission cost of one batched query on graph `graph` with output type
+ * out_type (host *bytes): n * (1 for BFS_OUT_U8, 4 for BFS_OUT_I32) + 24 * n / 64
+ * bytes, n the graph's vertex count. BFS_ERR_CAPACITY without lane memory.
+ */
+bfs_status bfs_batch_query_bytes(bfs_plan_t p, int32_t graph, int32_t out_type, int64_t *bytes);
+
+/* Counters of the batched engine over the caller's queries (the batch
+   autotuner's runs at plan creation are not counted). */
+typedef struct {
+  int64_t launches;             /* level-loop launches */
+  int64_t levels;               /* levels run over all launches */
+  int64_t admitted;             /* queries admitted into slots */
+  int64_t admitted_midflight;   /* of them, admitted while other queries were in flight */
+  int64_t max_inflight;         /* largest number of queries in flight at once */
+  int64_t max_inflight_bytes;   /* largest admission cost in flight at once */
+  int64_t inflight_bytes;       /* admission cost in flight now */
+} bfs_batch_counters;
+
+bfs_status bfs_batch_read_counters(bfs_plan_t p, bfs_batch_counters *out);
 
 /*
  * Settings of the batched engine (host *out): grid_blocks of its cooperative

@@ -46,7 +46,8 @@ class bfs_options(ctypes.Structure):
                 ("exchange", EXCHANGE_FN), ("exchange_ctx", ctypes.c_void_p),
                 ("relabel", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("hot_words", ctypes.c_int32), ("sparse_div", ctypes.c_int32),
-                ("direction", ctypes.c_int32), ("mark_mode", ctypes.c_int32)]
+                ("direction", ctypes.c_int32), ("mark_mode", ctypes.c_int32),
+                ("mem_budget_bytes", ctypes.c_int64), ("tune_cache", ctypes.c_char_p)]
 
 
 class bfs_stats(ctypes.Structure):
@@ -72,6 +73,13 @@ class bfs_tuning(ctypes.Structure):
 class bfs_query(ctypes.Structure):
     _fields_ = [("graph", ctypes.c_int32), ("out_type", ctypes.c_int32),
                 ("source", ctypes.c_int64), ("out", ctypes.c_void_p)]
+
+
+class bfs_batch_counters(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("levels", ctypes.c_int64),
+                ("admitted", ctypes.c_int64), ("admitted_midflight", ctypes.c_int64),
+                ("max_inflight", ctypes.c_int64), ("max_inflight_bytes", ctypes.c_int64),
+                ("inflight_bytes", ctypes.c_int64)]
 
 
 class bfs_batch_result(ctypes.Structure):
@@ -115,6 +123,8 @@ def lib():
         "bfs_batch_times": (i32, [vp, u64, vp, i32]),
         "bfs_batch_poll": (i32, [vp, vp, i32, ctypes.POINTER(i32), i64]),
         "bfs_batch_tuning": (i32, [vp, ctypes.POINTER(bfs_tuning)]),
+        "bfs_batch_query_bytes": (i32, [vp, i32, i32, ctypes.POINTER(i64)]),
+        "bfs_batch_read_counters": (i32, [vp, ctypes.POINTER(bfs_batch_counters)]),
         "bfs_frontier_list": (i32, [vp, vp, i64, ctypes.POINTER(i64)]),
         "bfs_expand_bottom_up": (i32, [vp, ctypes.POINTER(vp)]),
         "bfs_merge_lists": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), i32,
@@ -133,7 +143,8 @@ EXPORTED = ("bfs_options_default", "bfs_workspace_size", "bfs_plan_create", "bfs
             "bfs_last_error", "bfs_run", "bfs_begin", "bfs_expand", "bfs_merge_frontier",
             "bfs_finish", "bfs_level_stats", "bfs_level_times", "bfs_plan_tuning", "bfs_batch_submit",
             "bfs_batch_wait", "bfs_batch_times", "bfs_batch_poll", "bfs_batch_tuning",
-            "bfs_frontier_list", "bfs_merge_lists", "bfs_expand_bottom_up", "bfs_run_noalloc")
+            "bfs_frontier_list", "bfs_merge_lists", "bfs_expand_bottom_up", "bfs_run_noalloc",
+            "bfs_batch_query_bytes", "bfs_batch_read_counters")
 
 NOALLOC_MAX_VERTICES = 1 << 19
 NOALLOC_MAX_EDGES = 1 << 25
@@ -227,7 +238,8 @@ class Plan:
 
     def __init__(self, graphs, *, loop_mode=LOOP_AUTO, small_bin=0, wave_bin=0, chunk_edges=0,
                  grid_blocks=0, batch_lanes=0, collect_stats=False, exchange=None, stream=None,
-                 relabel=0, autotune=0, hot_words=0, sparse_div=0, direction=0, mark_mode=0):
+                 relabel=0, autotune=0, hot_words=0, sparse_div=0, direction=0, mark_mode=0,
+                 mem_budget_bytes=0, tune_cache=None):
         torch = _torch()
         L = lib()
         if isinstance(graphs, DeviceGraph):
@@ -247,6 +259,9 @@ class Plan:
         o.sparse_div = int(sparse_div)
         o.direction = int(direction)
         o.mark_mode = int(mark_mode)
+        o.mem_budget_bytes = int(mem_budget_bytes)
+        self._tune_cache = tune_cache.encode() if tune_cache else None
+        o.tune_cache = self._tune_cache
         self._exchange_py = exchange
         self._exchange_keep = None
         if exchange is not None:
@@ -429,6 +444,18 @@ class Plan:
         self._check(lib().bfs_batch_poll(self.h, buf.ctypes.data, max_tickets, ctypes.byref(n),
                                          timeout_us))
         return [int(x) for x in buf[:n.value]]
+
+    def batch_query_bytes(self, graph: int, out_type: int = OUT_I32) -> int:
+        """Admission cost of one batched query on `graph` (bytes)."""
+        b = ctypes.c_int64(0)
+        self._check(lib().bfs_batch_query_bytes(self.h, graph, out_type, ctypes.byref(b)))
+        return int(b.value)
+
+    def batch_counters(self) -> dict:
+        """Counters of the batched engine over the caller's queries."""
+        c = bfs_batch_counters()
+        self._check(lib().bfs_batch_read_counters(self.h, ctypes.byref(c)))
+        return {f: getattr(c, f) for f, _ in bfs_batch_counters._fields_}
 
     def batch_times(self, ticket: int, nq: int) -> np.ndarray:
         out = np.zeros(nq, dtype=np.int64)

@@ -4,12 +4,16 @@
 // cooperative persistent loop with either register budget and several grid
 // sizes, or one workgroup for small graphs), the degree-bin thresholds that
 // split the frontier into the lane-group, wavefront and chunked tiers, the
-// hub chunk size, the LDS hub copy and the queue-only level threshold.
-// Settings given explicitly in the options are never changed.
+// hub chunk size, the LDS hub copy, the queue-only level threshold and, for
+// all-dense traversals, byte marks against atomic ORs. Settings given
+// explicitly in the options are never changed; a tuning cache file (the
+// tune_cache option) records the outcome per graph, device and options.
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstring>
 #include <vector>
 
 #include "plan.hpp"
@@ -87,11 +91,9 @@ bfs_status time_config(Plan *p, int32_t gi, const std::vector<int64_t> &srcs, fl
   return BFS_OK;
 }
 
-}  // namespace
-
-bfs_status autotune_graphs(Plan *p) {
-  for (size_t gi = 0; gi < p->graphs.size(); ++gi) {
-    if (!tune_wanted(p, gi) || !p->lay.tune_dist) continue;
+// Times the candidates for graph gi and leaves the fastest in p->tune[gi].
+bfs_status tune_graph(Plan *p, size_t gi) {
+  {
     std::vector<int64_t> src;
     bfs_status s = pick_sources(p, gi, src);
     if (s) return s;
@@ -172,7 +174,7 @@ bfs_status autotune_graphs(Plan *p) {
     t = best;
     if (best.loop_mode == BFS_LOOP_CU) {  // the tier settings do not apply
       t.tuned_ms = best_ms / (float)src.size();
-      continue;
+      return BFS_OK;
     }
     // 2. tier thresholds (degree bins), each kept only if it helps
     if (p->opt.small_bin <= 0)
@@ -217,7 +219,130 @@ bfs_status autotune_graphs(Plan *p) {
         if ((s = trial(c))) return s;
       }
     t = best;
+    // all-dense levels: byte marks against atomic ORs into the bitmap
+    if (p->opt.mark_mode == 0 && best.sparse_div == 0) {
+      Tuning c = best;
+      c.mark = 0;
+      if ((s = trial(c))) return s;
+    }
+    t = best;
     t.tuned_ms = best_ms / (float)src.size();
+  }
+  return BFS_OK;
+}
+
+// Tuning cache. A line per tuned graph:
+//   bfs-tune <key> loop= variant= grid= small= wave= chunk= sparse= hot= mark= ms=
+// The key hashes (FNV-1a, 64 bits) the device (name, architecture, compute
+// units), the graph's sizes and 129 sampled row offsets and column ids, and
+// every option the autotuner must respect.
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void add(const void *d, size_t n) {
+    const unsigned char *c = (const unsigned char *)d;
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  }
+  template <class T>
+  void add(const T &x) {
+    add(&x, sizeof(T));
+  }
+};
+
+bfs_status tune_key(Plan *p, size_t gi, uint64_t &key) {
+  const bfs_graph &g = p->graphs[gi];
+  Fnv f;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return p->fail(BFS_ERR_HIP, "tune cache: no device properties");
+  f.add(prop.name, strnlen(prop.name, sizeof(prop.name)));
+  f.add(prop.gcnArchName, strnlen(prop.gcnArchName, sizeof(prop.gcnArchName)));
+  f.add(p->num_cus);
+  f.add(g.n_global);
+  f.add(g.v_begin);
+  f.add(g.v_end);
+  f.add(g.m);
+  const int64_t nrows = g.v_end - g.v_begin;
+  for (int k = 0; k <= 64; ++k) {
+    int64_t v = 0;
+    hipError_t e = hipMemcpy(&v, g.row_ptr + nrows * k / 64, sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return p->hip_fail(e, "tune cache key");
+    f.add(v);
+  }
+  for (int k = 0; k < 64 && g.m > 0; ++k) {
+    int32_t c = 0;
+    hipError_t e = hipMemcpy(&c, g.col + g.m * k / 64, sizeof(c), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return p->hip_fail(e, "tune cache key");
+    f.add(c);
+  }
+  const bfs_options &o = p->opt;
+  const int32_t opts[] = {o.loop_mode, o.small_bin, o.wave_bin, o.chunk_edges, o.grid_blocks, o.relabel,
+                          o.hot_words, o.sparse_div, o.direction, o.mark_mode};
+  f.add(opts, sizeof(opts));
+  key = f.h;
+  return BFS_OK;
+}
+
+bool read_cache(const char *path, uint64_t key, Tuning &t) {
+  FILE *fp = fopen(path, "r");
+  if (!fp) return false;
+  char line[512];
+  bool found = false;
+  Tuning c = t;
+  while (fgets(line, sizeof(line), fp)) {
+    unsigned long long k = 0;
+    int loop, var, grid, sb, wb, cs, sd, hw, mk;
+    float ms;
+    if (sscanf(line, "bfs-tune %llx loop=%d variant=%d grid=%d small=%d wave=%d chunk=%d sparse=%d hot=%d "
+                     "mark=%d ms=%f",
+               &k, &loop, &var, &grid, &sb, &wb, &cs, &sd, &hw, &mk, &ms) != 11)
+      continue;
+    if ((uint64_t)k != key) continue;
+    c.loop_mode = loop;
+    c.persist_variant = var;
+    c.persist_grid = grid;
+    c.small_bin = sb;
+    c.wave_bin = wb;
+    c.chunk_shift = cs;
+    c.sparse_div = sd;
+    c.hot_words = hw;
+    c.mark = mk;
+    c.tuned_ms = ms;
+    found = true;  // the last matching line wins
+  }
+  fclose(fp);
+  if (found) t = c;
+  return found;
+}
+
+void append_cache(const char *path, uint64_t key, const Tuning &t) {
+  FILE *fp = fopen(path, "a");
+  if (!fp) return;  // an unwritable cache only costs the next plan a tuning run
+  char line[512];
+  const int n = snprintf(line, sizeof(line),
+                         "bfs-tune %016llx loop=%d variant=%d grid=%d small=%d wave=%d chunk=%d sparse=%d "
+                         "hot=%d mark=%d ms=%.9g\n",
+                         (unsigned long long)key, t.loop_mode, t.persist_variant, t.persist_grid, t.small_bin,
+                         t.wave_bin, t.chunk_shift, t.sparse_div, t.hot_words, t.mark, t.tuned_ms);
+  if (n > 0) (void)fwrite(line, 1, (size_t)n, fp);  // one write per line
+  fclose(fp);
+}
+
+}  // namespace
+
+bfs_status autotune_graphs(Plan *p) {
+  const char *cache = (p->opt.tune_cache && *p->opt.tune_cache) ? p->opt.tune_cache : nullptr;
+  for (size_t gi = 0; gi < p->graphs.size(); ++gi) {
+    if (!tune_wanted(p, gi) || !p->lay.tune_dist) continue;
+    uint64_t key = 0;
+    if (cache) {
+      bfs_status s = tune_key(p, gi, key);
+      if (s) return s;
+      if (read_cache(cache, key, p->tune[gi])) continue;
+    }
+    bfs_status s = tune_graph(p, gi);
+    if (s) return s;
+    if (cache) append_cache(cache, key, p->tune[gi]);
   }
   return BFS_OK;
 }

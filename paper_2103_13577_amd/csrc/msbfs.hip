@@ -46,7 +46,14 @@ struct MsQuery {
   int32_t index_in_ticket = 0;
   int32_t status = BFS_OK;
   int64_t complete_ns = 0;
+  int64_t bytes = 0;  // admission cost
 };
+
+// Admission cost of a query: its distance output and its share of the three
+// lane-word arrays (8 bytes per 64 sources per vertex each).
+int64_t query_bytes(int64_t n, int32_t out_type) {
+  return n * (out_type == BFS_OUT_U8 ? 1 : 4) + 24 * n / 64;
+}
 
 struct MsTicket {
   int32_t nq = 0;
@@ -82,6 +89,9 @@ struct BatchState {
   hipStream_t stream = nullptr;
 
   int64_t launches = 0, levels_total = 0;
+  int64_t budget = 0;            // mem_budget_bytes (0: slots only)
+  int64_t inflight_bytes = 0;    // admission cost of the queries in slots
+  int64_t admitted = 0, admitted_midflight = 0, max_inflight = 0, max_inflight_bytes = 0;
   int32_t last_level = 0;       // global level clock of the engine
   bool streaming_mode = false;  // a streaming ticket was submitted
   float tuned_ms = 0.f;         // batch autotuner: best one-launch batch time (0: not tuned)
@@ -342,6 +352,7 @@ bfs_status batch_init(Plan *p) {
     delete b;
     return p->fail(BFS_ERR_HIP, "cooperative launch of the batched loop is not available");
   }
+  b->budget = std::max<int64_t>(p->opt.mem_budget_bytes, 0);
   b->pending.resize(ng);
   b->slot_q.resize(nslot);
   b->active.assign((size_t)ng * lw, 0);
@@ -355,6 +366,9 @@ bfs_status batch_init(Plan *p) {
     delete b;
     return st;
   }
+  // the counters describe the caller's queries, not the autotuner's batches
+  b->launches = b->levels_total = 0;
+  b->admitted = b->admitted_midflight = b->max_inflight = b->max_inflight_bytes = 0;
   b->worker = std::thread([b] { b->run(); });
   return BFS_OK;
 }
@@ -411,14 +425,24 @@ bool BatchState::step(std::unique_lock<std::mutex> &lk) {
         if (~used) slot = (g * lw + l) * 64 + __builtin_ctzll(~used);
       }
       if (slot < 0) break;
+      if (budget > 0 && inflight_bytes + q.front().bytes > budget) break;
       MsQuery mq = q.front();
       q.pop_front();
+      inflight_bytes += mq.bytes;
+      admitted += 1;
+      if (any_active) admitted_midflight += 1;
       active[slot / 64] |= 1ull << (slot % 64);
       slot_q[slot] = mq;
       h_adm[nadm++] = MsAdmit{ghost[g].off + mq.src, mq.src, ghost[g].n, (uint64_t)mq.out, mq.type,
                               slot};
       maxn = std::max(maxn, ghost[g].n);
     }
+  }
+  {
+    int64_t nact = 0;
+    for (int i = 0; i < nslotw; ++i) nact += __builtin_popcountll(active[i]);
+    max_inflight = std::max(max_inflight, nact);
+    max_inflight_bytes = std::max(max_inflight_bytes, inflight_bytes);
   }
   // A streaming launch stops early only when a slot of a graph with waiting
   // queries finishes (the freed slot can then be refilled); slots of other
@@ -480,6 +504,7 @@ bool BatchState::step(std::unique_lock<std::mutex> &lk) {
         if (t.done == t.nq) completed.push_back(slot_q[s].ticket);
       }
     std::fill(active.begin(), active.end(), 0);
+    inflight_bytes = 0;
     stop = true;
     cv_done.notify_all();
     return false;
@@ -509,6 +534,7 @@ bool BatchState::step(std::unique_lock<std::mutex> &lk) {
       }
       active[i] &= ~(1ull << b);
       dirty[i] |= 1ull << b;
+      inflight_bytes -= mq.bytes;
     }
   }
   if (depth_clear) {
@@ -558,6 +584,11 @@ bfs_status bfs_batch_submit(bfs_plan_t p, const bfs_query *q, int32_t nq, uint32
     if (!q[i].out) return p->fail(BFS_ERR_ARG, "query output is NULL");
     if (q[i].out_type != BFS_OUT_U8 && q[i].out_type != BFS_OUT_I32)
       return p->fail(BFS_ERR_ARG, "query out_type must be BFS_OUT_U8 or BFS_OUT_I32");
+    const int64_t qb = query_bytes(b->ghost[q[i].graph].n, q[i].out_type);
+    if (b->budget > 0 && qb > b->budget)
+      return p->fail(BFS_ERR_CAPACITY, "query " + std::to_string(i) + " needs " + std::to_string(qb) +
+                                           " bytes in flight, more than mem_budget_bytes (" +
+                                           std::to_string(b->budget) + "): it can never be admitted");
   }
   {
     std::lock_guard<std::mutex> lk(b->mu);
@@ -576,6 +607,7 @@ bfs_status bfs_batch_submit(bfs_plan_t p, const bfs_query *q, int32_t nq, uint32
       mq.out = q[i].out;
       mq.ticket = t;
       mq.index_in_ticket = i;
+      mq.bytes = query_bytes(b->ghost[mq.graph].n, mq.type);
       b->pending[mq.graph].push_back(mq);
     }
     if (nq == 0) {
@@ -645,6 +677,32 @@ bfs_status bfs_batch_times(bfs_plan_t p, uint64_t ticket, int64_t *complete_ns, 
   const MsTicket &t = it->second;
   if (t.done < t.nq) return p->fail(BFS_ERR_STATE, "ticket not finished");
   for (int i = 0; i < std::min(nq, t.nq); ++i) complete_ns[i] = t.times[i];
+  return BFS_OK;
+}
+
+bfs_status bfs_batch_query_bytes(bfs_plan_t p, int32_t graph, int32_t out_type, int64_t *bytes) {
+  if (!p) return BFS_ERR_ARG;
+  BatchState *b = p->batch;
+  if (!b) return p->fail(BFS_ERR_CAPACITY, "plan has no lane memory for batched queries");
+  if (graph < 0 || graph >= b->ng || !bytes || (out_type != BFS_OUT_U8 && out_type != BFS_OUT_I32))
+    return p->fail(BFS_ERR_ARG, "bad graph index, output type or NULL output");
+  *bytes = query_bytes(b->ghost[graph].n, out_type);
+  return BFS_OK;
+}
+
+bfs_status bfs_batch_read_counters(bfs_plan_t p, bfs_batch_counters *out) {
+  if (!p) return BFS_ERR_ARG;
+  BatchState *b = p->batch;
+  if (!b) return p->fail(BFS_ERR_CAPACITY, "plan has no lane memory for batched queries");
+  if (!out) return p->fail(BFS_ERR_ARG, "NULL output");
+  std::lock_guard<std::mutex> lk(b->mu);
+  out->launches = b->launches;
+  out->levels = b->levels_total;
+  out->admitted = b->admitted;
+  out->admitted_midflight = b->admitted_midflight;
+  out->max_inflight = b->max_inflight;
+  out->max_inflight_bytes = b->max_inflight_bytes;
+  out->inflight_bytes = b->inflight_bytes;
   return BFS_OK;
 }
 

@@ -120,8 +120,64 @@ def test_streaming_alone_equals_in_mix(gpu):
         d, _, _ = alone.run(gi, s)
         assert np.array_equal(out.cpu().numpy(), d.cpu().numpy()), (gi, s)
         assert np.array_equal(out.cpu().numpy(), oracle.bfs(gs[gi], s)), (gi, s)
+    c = plan.batch_counters()
+    print(f"[gpu] streaming counters {c}", flush=True)
+    assert c["admitted"] == len(items)
+    # continuous batching: queries joined while others were in flight
+    assert c["admitted_midflight"] > 0 and c["max_inflight"] > 1
+    assert c["inflight_bytes"] == 0
     plan.close()
     alone.close()
+
+
+def test_memory_budget_admission(gpu):
+    """Streaming queries are admitted by memory (a query's int32 output plus
+    its lane share): under a budget of two and a half queries at most two are
+    in flight at once, every query still completes exactly, and the budget is
+    the only limit (the plan has 64 slots)."""
+    import torch
+    g = gg.rmat(14, 8, seed=61, perm_seed=62)
+    dg = pkg.DeviceGraph.from_csr(g, gpu)
+    probe = pkg.Plan([dg], batch_lanes=1, autotune=-1)
+    qb = probe.batch_query_bytes(0, pkg.OUT_I32)
+    assert qb == 4 * g.n + 24 * g.n // 64
+    assert probe.batch_query_bytes(0, pkg.OUT_U8) == g.n + 24 * g.n // 64
+    probe.close()
+    budget = qb * 5 // 2
+    plan = pkg.Plan([dg], batch_lanes=1, autotune=-1, mem_budget_bytes=budget)
+    srcs = [int(s) for s in gg.pick_sources(g, 12, seed=63)]
+    outs = [torch.empty(g.n, dtype=torch.int32, device=gpu) for _ in srcs]
+    t = plan.batch_submit([(0, s, o) for s, o in zip(srcs, outs)], pkg.BATCH_STREAMING)
+    plan.batch_wait(t)
+    for s, o in zip(srcs, outs):
+        assert np.array_equal(o.cpu().numpy(), oracle.bfs(g, s)), s
+    c = plan.batch_counters()
+    print(f"[gpu] budget counters {c}", flush=True)
+    assert c["admitted"] == len(srcs)
+    assert c["max_inflight"] == 2 and c["max_inflight_bytes"] <= budget
+    assert c["inflight_bytes"] == 0
+    plan.close()
+
+
+def test_memory_budget_refuses_never_admissible(gpu):
+    """A query whose own admission cost exceeds the budget can never run: the
+    submission is refused with BFS_ERR_CAPACITY (nothing of it is queued), and
+    a query that fits is still served."""
+    import torch
+    g = gg.rmat(13, 8, seed=64, perm_seed=65)
+    dg = pkg.DeviceGraph.from_csr(g, gpu)
+    budget = 2 * g.n  # fits a uint8 query (n + 24n/64), not an int32 one (4n + 24n/64)
+    plan = pkg.Plan([dg], batch_lanes=1, autotune=-1, mem_budget_bytes=budget)
+    s = int(gg.pick_sources(g, 1, seed=66)[0])
+    o32 = torch.empty(g.n, dtype=torch.int32, device=gpu)
+    o8 = torch.empty(g.n, dtype=torch.uint8, device=gpu)
+    with pytest.raises(pkg.BfsError) as e:
+        plan.batch_submit([(0, s, o8), (0, s, o32)], pkg.BATCH_STREAMING)
+    assert e.value.status == 5
+    assert plan.batch_counters()["admitted"] == 0
+    plan.batch_wait(plan.batch_submit([(0, s, o8)], pkg.BATCH_STREAMING))
+    assert np.array_equal(o8.cpu().numpy(), _oracle_out(g, s, "u8"))
+    plan.close()
 
 
 def test_batch_errors(gpu):

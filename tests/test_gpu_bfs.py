@@ -871,3 +871,33 @@ def test_run_allocates_nothing(gpu, plan_opts):
     free1, _ = torch.cuda.mem_get_info()
     assert free1 == free0, (free0, free1, plan.tuning(0))
     plan.close()
+
+
+def test_tune_cache(gpu, tmp_path):
+    """A plan with a tuning cache appends its tuned settings; a second plan on
+    the same graph, device and options takes them from the cache (no timing
+    runs) and traverses exactly; other options make another entry."""
+    import time as _time
+    g = gg.rmat(15, 16, seed=71, perm_seed=72)
+    dg = pkg.DeviceGraph.from_csr(g, gpu)
+    path = str(tmp_path / "bfs_tune.txt")
+    t0 = _time.perf_counter()
+    a = pkg.Plan([dg], autotune=1, tune_cache=path)
+    ta = _time.perf_counter() - t0
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("bfs-tune ")
+    t0 = _time.perf_counter()
+    b = pkg.Plan([dg], autotune=1, tune_cache=path)
+    tb = _time.perf_counter() - t0
+    assert len(open(path).read().splitlines()) == 1  # read, not re-tuned
+    assert a.tuning(0) == b.tuning(0)
+    assert tb < ta
+    s = int(gg.pick_sources(g, 1, seed=73)[0])
+    d, _, _ = b.run(0, s)
+    assert np.array_equal(d.cpu().numpy(), oracle.bfs(g, s))
+    c = pkg.Plan([dg], autotune=1, tune_cache=path, small_bin=5)
+    assert len(open(path).read().splitlines()) == 2
+    assert c.tuning(0)["small_bin"] == 5
+    a.close()
+    b.close()
+    c.close()
