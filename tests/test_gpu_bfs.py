@@ -583,6 +583,48 @@ def _read_device_words(addr, W, gpu):
     return out
 
 
+def test_partition_share_scale26(gpu):
+    """Partition 0 of a 16-way 1D partition of R-MAT scale 26, edge factor 8,
+    with the four radix-2 butterfly messages of every level staged from the
+    oracle: 2^26-bit (8 MiB) bitmaps, so every merge block strides over
+    several steps. The node's global next bitmap after each expansion equals
+    the oracle's X_0(L) bit for bit, the level counts match, and the whole
+    distance array equals the oracle's."""
+    import torch
+    print("[gpu] generating rmat26 ef8", flush=True)
+    g = gg.rmat(26, 8, seed=0x5EED0026, perm_seed=0xBEEF0026)
+    src = int(gg.pick_sources(g, 1, seed=0xC0FFEE26)[0])
+    ref = oracle.bfs(g, src)
+    b = gg.partition_1d(g.row_ptr, 16)
+    local, inc = oracle.stage(g, ref, b, 0, 2)
+    print(f"[gpu] share26 staged {local.shape[0]} levels", flush=True)
+    dg = pkg.DeviceGraph.from_csr(g, gpu, 0, int(b[1]))
+    plan = pkg.Plan([dg])
+    dist = torch.empty(g.n, dtype=torch.int32, device=gpu)
+    W = (g.n + 63) // 64
+    zeros = [torch.zeros(W, dtype=torch.int64, device=gpu) for _ in range(inc.shape[1])]
+    plan.begin(0, src, dist)
+    L = 0
+    while True:
+        addr = plan.expand()
+        got = _read_device_words(addr, W, gpu)
+        exp = local[L] if L < local.shape[0] else np.zeros(W, dtype=np.uint64)
+        assert np.array_equal(got, exp), f"local next at level {L}"
+        msgs = [_words_to_tensor(inc[L, j], gpu) for j in range(inc.shape[1])] if L < local.shape[0] else zeros
+        gnew, onew = plan.merge_frontier(msgs)
+        assert gnew == int((ref == L + 1).sum())
+        assert onew == int((ref == L + 1)[b[0]:b[1]].sum())
+        del msgs
+        if gnew == 0:
+            break
+        L += 1
+    st = plan.finish()
+    assert st.levels == int(ref.max()) + 1
+    assert np.array_equal(dist.cpu().numpy(), ref)
+    assert st.edges_scanned == oracle.edges_scanned(g, ref, int(b[0]), int(b[1]))
+    plan.close()
+
+
 @pytest.mark.parametrize("rounds", [False, True])
 def test_partition_share_run_with_exchange(gpu, rounds):
     """bfs_run with an exchange callback serving the staged messages; with
