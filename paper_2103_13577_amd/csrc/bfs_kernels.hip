@@ -440,6 +440,30 @@ __device__ __forceinline__ void probe_dispatch(const View &v, const int32_t (&u)
   else probe_batch<K>(v, u, ok, hot);
 }
 
+// One batch of K rows of a tier-0 group's dealt edges, starting at edge e0 of
+// the group (edges at or beyond `total` are masked off).
+template <bool SPARSE, int K>
+__device__ __forceinline__ void deal_rows(const View &v, int32_t incl, int64_t rebase, int32_t e0,
+                                          int32_t total, int level, SparseAcc &acc, HotCache hot,
+                                          int32_t *dist) {
+  const int lane = lane_id();
+  int32_t u[K];
+  bool ok[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int32_t e = e0 + j * kWave + lane;
+    int k = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1)
+      if (__shfl(incl, k + step - 1) <= e) k += step;
+    k = min(k, kWave - 1);
+    const int64_t rk = shfl64(rebase, k);
+    ok[j] = e < total;
+    u[j] = ok[j] ? load_col(v.col, rk + e) : 0;
+  }
+  probe_dispatch<SPARSE, K>(v, u, ok, level, acc, hot, dist);
+}
+
 // Expansion of level `level` by virtual block `vb_id` of `nvb` blocks. Block 0
 // first clears the counters of the ring slot two levels ahead (read at level
 // L-1, not written before level L+1). Every loop below runs the same number
@@ -553,23 +577,20 @@ __device__ __forceinline__ void expand_phase(const View &v, int32_t *dist, int l
     // lane with incl[k] > e: its column index is col[start[k] - excl[k] + e]
     const int64_t rebase = start - (int64_t)(incl - deg);
     scanned += (uint64_t)total;
-    for (int32_t e0 = 0; e0 < total; e0 += kWave * KS) {
-      int32_t u[KS];
-      bool ok[KS];
-#pragma unroll
-      for (int j = 0; j < KS; ++j) {
-        const int32_t e = e0 + j * kWave + lane;
-        int k = 0;
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1)
-          if (__shfl(incl, k + step - 1) <= e) k += step;
-        k = min(k, kWave - 1);
-        const int64_t rk = shfl64(rebase, k);
-        ok[j] = e < total;
-        u[j] = ok[j] ? load_col(v.col, rk + e) : 0;
-      }
-      probe_dispatch<SPARSE, KS>(v, u, ok, level, acc, hot, dist);
+    // a group whose edges fill at most a quarter (a half) of a batch, the
+    // common case on the late levels of power-law graphs, takes a batch of a
+    // quarter (a half) the rows: the dealing arithmetic of empty rows is not
+    // issued
+    if (KS >= 8 && total <= kWave * (KS / 4)) {
+      deal_rows<SPARSE, KS / 4>(v, incl, rebase, 0, total, level, acc, hot, dist);
+      continue;
     }
+    if (KS >= 4 && total <= kWave * (KS / 2)) {
+      deal_rows<SPARSE, KS / 2>(v, incl, rebase, 0, total, level, acc, hot, dist);
+      continue;
+    }
+    for (int32_t e0 = 0; e0 < total; e0 += kWave * KS)
+      deal_rows<SPARSE, KS>(v, incl, rebase, e0, total, level, acc, hot, dist);
   }
 
   if (!SPARSE) {
