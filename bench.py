@@ -990,6 +990,49 @@ def summarize_trace(args):
     print("\n".join(md))
 
 
+def summarize_counters(args):
+    """Writes a markdown table of rocprofv3 --pmc counters of a bench.py run:
+    for the dominant kernel series the mean per launch over the timed
+    region's launches, for every other kernel the mean per dispatch over the
+    dispatches from the first timed launch on."""
+    import csv
+    from collections import defaultdict
+
+    d, log, out_name, command = args.summarize_counters
+    line = _bench_line(log)
+    group = _dense_series(line["roofline"]["kernel"])
+    members = set(group.split("+"))
+    timed = line["roofline"].get("launches", 0)
+    per = defaultdict(lambda: defaultdict(lambda: defaultdict(float)))
+    with open(os.path.join(d, "run_counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            k = _short(r["Kernel_Name"])
+            per[k][int(r["Dispatch_Id"])][r["Counter_Name"]] += float(r["Counter_Value"])
+    dom = sorted(i for k in members for i in per.get(k, {}))
+    dom = dom[-timed:] if timed else dom
+    first = dom[0] if dom else 0
+    counters = sorted({c for k in per for i in per[k] for c in per[k][i]})
+    rows = []
+    for k in sorted(per, key=lambda k: (k not in members, k)):
+        ids = [i for i in per[k] if (i in dom if k in members else i >= first)]
+        if not ids:
+            continue
+        means = {c: sum(per[k][i].get(c, 0.0) for i in ids) / len(ids) for c in counters}
+        rows.append((k, len(ids), means))
+    md = [f"# rocprofv3 counters: {line['config']['workload']}", "",
+          "Command (from the repository root):", "", "```", command, "```", "",
+          f"Means per dispatch over the timed region (the last {timed} launches of "
+          f"`{group}`, and every other dispatch from the first of them on).", "",
+          "| kernel | dispatches | " + " | ".join(counters) + " |",
+          "|---|---|" + "---|" * len(counters)]
+    for k, n, means in rows:
+        md.append(f"| `{k}` | {n} | " + " | ".join(f"{means[c]:.4g}" for c in counters) + " |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", out_name), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 def copy_probe(nbytes):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -1040,6 +1083,8 @@ def main():
                                                          "COPY_WRITE_DIR", "FETCH_RUN_LOG"))
     ap.add_argument("--summarize-trace", nargs=4, metavar=("TRACE_DIR", "RUN_LOG", "OUT_NAME",
                                                            "COMMAND"))
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("PMC_DIR", "RUN_LOG", "OUT_NAME",
+                                                              "COMMAND"))
     ap.add_argument("--pmc-commands", nargs="*", default=[],
                     help="the rocprofv3 commands the --summarize-pmc runs came from (recorded)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
@@ -1058,6 +1103,9 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(args)
+        return
+    if args.summarize_counters:
+        summarize_counters(args)
         return
     if args.workload == "rmat24":
         out = run_single(args, "rmat24", 24, 16)

@@ -153,8 +153,10 @@ typedef struct {
    rule is the usual edge-count test). In the host-driven loop a level L >= 2
    runs bottom-up -- every unvisited vertex scans its adjacency for a member of
    the level-L frontier bitmap and stops at the first -- once the frontier's
-   edges exceed 1/14 of the unvisited vertices' edges, and returns to top-down
-   when the frontier shrinks below n/24 vertices. */
+   edges exceed 1/14 of the unvisited vertices' edges and n/24, and returns
+   to top-down
+   once the frontier is below n/24 vertices and no larger than the previous
+   level's (so a long tail of small levels runs top-down). */
 #define BFS_DIR_OPTIMIZING 1
 
 /* Fills *o with defaults (all zero / NULL, loop_mode AUTO). */

@@ -830,8 +830,11 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
         const int64_t mu = g.m - p->edges_after[L - 1];
         const int64_t nf = p->level_frontier[L], nf_prev = p->level_frontier[L - 1];
         if (!p->bu_state) {
-          if (mf * kDirAlpha > mu) p->bu_state = true;
-        } else if (nf * kDirBeta < g.n_global && nf < nf_prev) {
+          // a frontier with few edges stays top-down even when fewer remain
+          // (the end of a long tail): a bottom-up step costs at least a sweep
+          // over the unvisited vertices, a top-down one only the frontier's edges
+          if (mf * kDirAlpha > mu && mf * kDirBeta >= g.n_global) p->bu_state = true;
+        } else if (nf * kDirBeta < g.n_global && nf <= nf_prev) {
           p->bu_state = false;
         }
         if (p->bu_state) {

@@ -17,7 +17,7 @@ constexpr uint32_t kNarrowHotMax = 4096;  // larger LDS hub copies use the wide 
 constexpr uint32_t kQueueOnly = 0xFFFFFFFFu;  // k_expand: run a queue-only level
 constexpr uint32_t kBottomUpHot = 2048;       // frontier words a bottom-up block keeps in LDS
 constexpr int64_t kDirAlpha = 14;  // top-down -> bottom-up when frontier edges * 14 > unvisited edges
-constexpr int64_t kDirBeta = 24;   // bottom-up -> top-down when frontier * 24 < n and shrinking
+constexpr int64_t kDirBeta = 24;   // bottom-up -> top-down when frontier * 24 < n and not growing
 constexpr int kMaxStatLevels = 4096;
 constexpr int kListMaxBlocks = 2048;  // blocks of the list export (count scratch: 2049 words)
 constexpr int32_t kErrListId = 4;     // Ctl::err bit: a received list held an id outside [0, n)

@@ -213,11 +213,13 @@ def test_direction_optimizing_returns_top_down(gpu, opts):
         assert st.edges_scanned == oracle.edges_scanned(g, ref)
         assert st.reached == int((ref >= 0).sum())
         assert st.levels == int(ref.max()) + 1
-        # levels 0 and 1 run top-down and the core's largest level (2, else 3)
-        # bottom-up (its frontier's edges are 13x the unvisited edges), so more
-        # than three top-down levels include some after the bottom-up ones
-        assert st.bottom_up_levels > 0
-        assert st.levels - st.bottom_up_levels > 3
+        # levels 0 and 1 run top-down and the core's large levels bottom-up
+        # (the frontier's edges exceed 1/14 of the unvisited edges and n/24);
+        # once the frontier is small and not growing the traversal returns to
+        # top-down, and a frontier with few edges never enters bottom-up, so
+        # every level of the 40-vertex path runs top-down
+        assert 0 < st.bottom_up_levels <= 4
+        assert st.levels - st.bottom_up_levels >= 42
     plan.close()
 
 
