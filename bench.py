@@ -149,7 +149,7 @@ def headline_sources(g, count):
 
 
 # Settings of the scale-24 headline plan (see run_single).
-HEADLINE_PLAN = dict(loop_mode=1, small_bin=8, wave_bin=15, chunk_edges=1024, hot_words=16384,
+HEADLINE_PLAN = dict(loop_mode=1, small_bin=8, wave_bin=15, chunk_edges=1024, hot_words=20352,
                      sparse_div=-1, relabel=1, autotune=-1)
 
 
@@ -586,6 +586,60 @@ def run_serve(args):
     return out
 
 
+def run_batch_grid(args):
+    """Per-level cost of the batched engine on the serving pool's two
+    16M-vertex grids (4096x4096 and 16384x1024, 1% of edges deleted), whose
+    thousands of levels dominate the serving latency: one-launch batches of 1
+    and 64 sources per grid (uint8 outputs are not enough for these depths:
+    int32), against single-source bfs_run (autotuned) on the same sources."""
+    import torch
+    import paper_2103_13577_amd as pkg
+    dev = torch.device("cuda:0")
+    pool = [x for x in _serve_pool() if x[0].startswith("grid")]
+    gs = [make() for _, make in pool]
+    dgs = [pkg.DeviceGraph.from_csr(g, dev) for g in gs]
+    plan = pkg.Plan(dgs, batch_lanes=1, autotune=-1)
+    single = pkg.Plan(dgs)
+    res = {}
+    for gi, (name, _) in enumerate(pool):
+        g = gs[gi]
+        srcs = [int(s) for s in gg.pick_sources(g, 64, seed=0x5EED0590 + gi)]
+        row = {}
+        for nsrc in (1, 64):
+            outs = [torch.empty(g.n, dtype=torch.int32, device=dev) for _ in range(nsrc)]
+            qs = [(gi, s, o) for s, o in zip(srcs[:nsrc], outs)]
+            plan.batch_wait(plan.batch_submit(qs, pkg.BATCH_ONE_LAUNCH))  # warm-up
+            c0 = plan.batch_counters()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            plan.batch_wait(plan.batch_submit(qs, pkg.BATCH_ONE_LAUNCH))
+            dt = time.perf_counter() - t
+            c1 = plan.batch_counters()
+            levels = c1["levels"] - c0["levels"]
+            ok = all(torch.equal(o, single.run(gi, s)[0]) for s, o in zip(srcs[:2], outs[:2]))
+            row[f"{nsrc}_sources"] = {"ms": round(dt * 1e3, 2), "levels": int(levels),
+                                       "us_per_level": round(dt * 1e6 / max(levels, 1), 2),
+                                       "launches": int(c1["launches"] - c0["launches"]),
+                                       "exact_vs_bfs_run": bool(ok)}
+            log(f"{name} {nsrc} sources: {row[f'{nsrc}_sources']}")
+        d, _, st = single.run(gi, srcs[0])
+        row["bfs_run_one_source"] = {"ms": round(st.ms, 2), "levels": int(st.levels),
+                                     "us_per_level": round(st.ms * 1e3 / max(st.levels, 1), 2),
+                                     "plan": single.tuning(gi)}
+        res[name] = row
+    out = {"metric": "batched engine per-level cost on the serving pool's grids",
+           "value": res[pool[0][0]]["64_sources"]["us_per_level"], "unit": "us/level",
+           "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "one-launch batches on grids 4096x4096 and 16384x1024 (1% edge "
+                                  "deletions), 1 and 64 sources per grid",
+                      "batch_tuning": plan.batch_tuning()},
+           "grids": res}
+    plan.close()
+    single.close()
+    return out
+
+
 # ---------------------------------------------------------------------------
 # one node's share of R-MAT scale 29 with staged butterfly messages
 # ---------------------------------------------------------------------------
@@ -804,6 +858,10 @@ def run_share29(args):
     k = 4
     merge_bytes = (k + 3) * W * 8
     mrg_gbs = merge_bytes / (np.mean(mrg_ms) * 1e-3) / 1e9
+    # the dense expansion of the share: 4 B per scanned edge and 16 B of row
+    # offsets per frontier vertex (counted on the device), over its launches
+    exp_bytes = 4.0 * st.dense_edges + 16.0 * st.dense_frontier
+    exp_gbs = exp_bytes / (float(np.sum(exp_ms)) * 1e-3) / 1e9
     out = {
         "metric": "GTEPS over the share's scanned edges (one node of 16, staged butterfly messages)",
         "value": round(metrics.gteps(e_share, float(np.median(tot)) * 1e-3), 3), "unit": "GTEPS",
@@ -818,7 +876,14 @@ def run_share29(args):
         "per_level_ms": {"expand": [round(x, 3) for x in exp_ms], "merge": [round(x, 3) for x in mrg_ms]},
         "roofline": {"bound": "hbm", "kernel": "k_merge", "achieved": round(mrg_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(mrg_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": int(merge_bytes)},
+                     "traffic": None, "bytes_per_launch": int(merge_bytes),
+                     "launches": len(runs) * len(mrg_ms)},
+        "roofline_expansion": {"bound": "hbm", "kernel": "k_expand", "achieved": round(exp_gbs, 1),
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(exp_gbs / HBM_PEAK_GBS, 4),
+                               "bytes_per_traversal": int(exp_bytes),
+                               "launches_per_traversal": len(exp_ms),
+                               "ms_per_traversal": round(float(np.sum(exp_ms)), 3)},
         "exact": bool(exact),
         "list_messages": {
             "note": "same traversal with every staged message of fewer than n/32 vertices sent as "
@@ -1050,7 +1115,7 @@ def main():
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat24",
-                    choices=["rmat24", "rmat14", "batch", "serve", "share29"])
+                    choices=["rmat24", "rmat14", "batch", "batch-grid", "serve", "share29"])
     ap.add_argument("--loop-mode", type=int, default=-1,
                     help="-1: for rmat24 the pinned headline plan (host-driven loop, each "
                          "expansion launch timed), else the tuned loop; 0: tuned; 1..4: BFS_LOOP_*")
@@ -1113,6 +1178,8 @@ def main():
         out = run_single(args, "rmat14", 14, 8)
     elif args.workload == "batch":
         out = run_batch(args)
+    elif args.workload == "batch-grid":
+        out = run_batch_grid(args)
     elif args.workload == "serve":
         out = run_serve(args)
     else:

@@ -371,7 +371,7 @@ bfs_status bfs_level_times(bfs_plan_t p, float *expand_ms, float *merge_ms, int3
  */
 #define BFS_NOALLOC_MAX_VERTICES (1 << 19)
 #define BFS_NOALLOC_MAX_EDGES (1 << 25)
-#define BFS_NOALLOC_SCRATCH_BYTES (8 * BFS_NOALLOC_MAX_VERTICES + 16384)
+#define BFS_NOALLOC_SCRATCH_BYTES (16 * BFS_NOALLOC_MAX_VERTICES + 16384)
 bfs_status bfs_run_noalloc(const bfs_graph *g, int64_t source, int32_t *dist, void *hip_stream,
                            int32_t *levels);
 

@@ -123,8 +123,8 @@ bfs_status tune_graph(Plan *p, size_t gi) {
       // the per-phase loops run the large levels with an LDS hub copy on a
       // relabelled graph, which the cooperative loop does not: compare them
       // with one too, or the loop choice is made without their main advantage
-      int hw = 16384;
-      while (hw > 1024 && (int64_t)hw * 8 + 1024 > p->max_lds) hw /= 2;
+      // the largest hub copy one workgroup's LDS holds (next to 1 KB of static LDS)
+      int hw = (int)std::min<int64_t>((p->max_lds - 1024) / 8, kMaxHotWords);
       if (p->lay.rl_rp[gi] && p->opt.hot_words == 0 && (int64_t)hw * 8 + 1024 <= p->max_lds) {
         h.hot_words = hw;
         h.loop_mode = BFS_LOOP_HOST;
@@ -197,7 +197,7 @@ bfs_status tune_graph(Plan *p, size_t gi) {
     t = best;
     // LDS copy of the hubs' visited bits (relabelled graphs only)
     if (p->lay.rl_rp[gi] && best.loop_mode != BFS_LOOP_PERSISTENT && p->opt.hot_words == 0)
-      for (int hw : {1024, 2048, 4096, 8192, 16384, 18432}) {
+      for (int hw : {1024, 2048, 4096, 8192, 16384, (int)std::min<int64_t>((p->max_lds - 1024) / 8, kMaxHotWords)}) {
         if ((int64_t)hw * 8 + 1024 > p->max_lds) continue;
         Tuning c = best;
         c.hot_words = hw;

@@ -32,6 +32,7 @@ namespace {
 constexpr int kCuBlock = 1024;
 constexpr int kCuWaves = kCuBlock / kWave;
 constexpr int kCuUnroll = 8;  // edges per lane in flight
+constexpr int kCuMergeWords = 4;  // bitmap words per wavefront step of the merge
 
 __device__ __forceinline__ void lds_or(uint64_t *p, uint64_t bit) {
   (void)__hip_atomic_fetch_or(p, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -39,8 +40,11 @@ __device__ __forceinline__ void lds_or(uint64_t *p, uint64_t bit) {
 
 // Requires a whole graph (owned range [0, n)) with m < 2^25 edges, so one
 // wavefront's edge prefix sums fit in 32 bits, 2 * words * 8 bytes of dynamic
-// LDS, and two queue buffers of n entries (q0[0], q0[1]). dist was reset by
-// k_reset.
+// LDS, and two queue buffers of n packed rows (qr0[0], qr0[1]): an entry is
+// the vertex's row start << 24 | its degree (the merge has just read both),
+// so the expansion goes from the queue straight to the column ids, and each
+// round's entries are requested while the previous round is expanded. dist
+// was reset by k_reset.
 __global__ void __launch_bounds__(kCuBlock) k_bfs_cu(View v, int64_t src_caller, int max_levels) {
   extern __shared__ uint64_t lds[];
   // an error flagged before the launch (an invalid graph) skips the traversal
@@ -58,7 +62,7 @@ __global__ void __launch_bounds__(kCuBlock) k_bfs_cu(View v, int64_t src_caller,
     nxt[w] = 0ull;
   }
   if (tid == 0) {
-    v.q0[0][0] = (int32_t)src;
+    v.qr0[0][0] = pack_row(v.rp[src], v.rp[src + 1] - v.rp[src]);
     s_qn[0] = 1;
     s_edges = 0;
   }
@@ -69,8 +73,8 @@ __global__ void __launch_bounds__(kCuBlock) k_bfs_cu(View v, int64_t src_caller,
   int L = 0;
   for (;; ++L) {
     const int cur = L & 1, nx = cur ^ 1;
-    const int32_t *q = v.q0[cur];
-    int32_t *qn = v.q0[nx];
+    const uint64_t *q = v.qr0[cur];
+    uint64_t *qn = v.qr0[nx];
     // queue counts are read as wave-uniform values, so the loop's exit test is
     // uniform and the compiler keeps every lane in every iteration
     const int64_t nq = __builtin_amdgcn_readfirstlane(s_qn[cur]);
@@ -81,15 +85,17 @@ __global__ void __launch_bounds__(kCuBlock) k_bfs_cu(View v, int64_t src_caller,
     if (v.stats && L + 2 < kMaxStatLevels && tid < kNumBins) v.lvl_hist[(L + 2) * kNumBins + tid] = 0;
     // expand: round r covers queue entries [r, r + 1024); lane l of wavefront
     // w takes entry r + w + 16 l
+    uint64_t pr_next = 0;
+    {
+      const int64_t i = wave + (int64_t)kCuWaves * lane;
+      if (i < nq) pr_next = q[i];
+    }
     for (int64_t r = 0; r < nq; r += kCuBlock) {
-      const int64_t i = r + wave + (int64_t)kCuWaves * lane;
-      int64_t start = 0;
-      int32_t deg = 0;
-      if (i < nq) {
-        const int64_t x = q[i];
-        start = v.rp[x];
-        deg = (int32_t)(v.rp[x + 1] - start);
-      }
+      const uint64_t pr = pr_next;
+      const int64_t i2 = r + kCuBlock + wave + (int64_t)kCuWaves * lane;
+      pr_next = i2 < nq ? q[i2] : 0ull;
+      const int64_t start = (int64_t)(pr >> kRowShift);
+      const int32_t deg = (int32_t)(pr & ((1ull << kRowShift) - 1));
       const int32_t incl = wave_incl_scan32(deg);
       const int32_t total = __shfl(incl, kWave - 1);
       const int64_t rebase = start - (int64_t)(incl - deg);
@@ -118,26 +124,44 @@ __global__ void __launch_bounds__(kCuBlock) k_bfs_cu(View v, int64_t src_caller,
       }
     }
     __syncthreads();
-    // merge
-    for (int64_t w = wave; w < W; w += kCuWaves) {
-      const uint64_t nw = nxt[w] & ~vis[w];
-      if (nw != 0ull) {
-        uint32_t base = 0;
-        if (lane == 0) {
-          base = __hip_atomic_fetch_add(&s_qn[nx], (uint32_t)__popcll(nw), __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_WORKGROUP);
-          vis[w] |= nw;
-        }
-        base = __shfl(base, 0);
-        if ((nw >> lane) & 1ull) {
+    // merge: kCuMergeWords words per wavefront step, their row-offset loads
+    // in flight together
+    for (int64_t w0 = (int64_t)wave * kCuMergeWords; w0 < W; w0 += (int64_t)kCuWaves * kCuMergeWords) {
+      uint64_t nw[kCuMergeWords];
+      int64_t r0[kCuMergeWords], r1[kCuMergeWords];
+#pragma unroll
+      for (int q = 0; q < kCuMergeWords; ++q) {
+        const int64_t w = w0 + q;
+        nw[q] = w < W ? nxt[w] & ~vis[w] : 0ull;
+        r0[q] = r1[q] = 0;
+        if ((nw[q] >> lane) & 1ull) {
           const int64_t x = w * 64 + lane;
-          v.dist[v.old_id ? (int64_t)v.old_id[x] : x] = L + 1;
-          qn[base + rank_below(nw)] = (int32_t)x;
-          if (v.stats && L + 1 < kMaxStatLevels)
-            atomic_add32(&v.lvl_hist[(L + 1) * kNumBins + degree_bin(v.rp[x + 1] - v.rp[x])], 1u);
+          r0[q] = v.rp[x];
+          r1[q] = v.rp[x + 1];
         }
       }
-      if (lane == 0) nxt[w] = 0ull;
+#pragma unroll
+      for (int q = 0; q < kCuMergeWords; ++q) {
+        const int64_t w = w0 + q;
+        if (w >= W) break;
+        if (nw[q] != 0ull) {
+          uint32_t base = 0;
+          if (lane == 0) {
+            base = __hip_atomic_fetch_add(&s_qn[nx], (uint32_t)__popcll(nw[q]), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+            vis[w] |= nw[q];
+          }
+          base = __shfl(base, 0);
+          if ((nw[q] >> lane) & 1ull) {
+            const int64_t x = w * 64 + lane;
+            v.dist[v.old_id ? (int64_t)v.old_id[x] : x] = L + 1;
+            qn[base + rank_below(nw[q])] = pack_row(r0[q], r1[q] - r0[q]);
+            if (v.stats && L + 1 < kMaxStatLevels)
+              atomic_add32(&v.lvl_hist[(L + 1) * kNumBins + degree_bin(r1[q] - r0[q])], 1u);
+          }
+        }
+        if (lane == 0) nxt[w] = 0ull;
+      }
     }
     __syncthreads();
     nn = __builtin_amdgcn_readfirstlane(s_qn[nx]);

@@ -4,7 +4,7 @@
 // level loop of bfs_run (BFS_LOOP_CU: both bitmaps in LDS, Algorithm 1 with
 // workgroup barriers between Phase 1 and Phase 2) with its device scratch --
 // the control block and the two frontier queues -- in a file-scope device
-// array of fixed size instead of a plan's workspace. Every call on a device
+// array of fixed size (8 MiB) instead of a plan's workspace. Every call on a device
 // shares that device's array, so calls that overlap on one device race.
 
 #include <hip/hip_runtime.h>
@@ -23,11 +23,11 @@ namespace {
 constexpr int64_t kNaMaxVertices = BFS_NOALLOC_MAX_VERTICES;
 constexpr int64_t kNaMaxEdges = BFS_NOALLOC_MAX_EDGES;
 constexpr size_t kNaCtlBytes = (sizeof(Ctl) + 255) / 256 * 256;
-constexpr size_t kNaQueueBytes = sizeof(int32_t) * (size_t)kNaMaxVertices;
+constexpr size_t kNaQueueBytes = sizeof(uint64_t) * (size_t)kNaMaxVertices;
 constexpr size_t kNaBytes = kNaCtlBytes + 2 * kNaQueueBytes;
 constexpr int kNaMaxDevices = 64;
 
-// Device scratch: control block, then queue buffers 0 and 1 (n entries each).
+// Device scratch: control block, then queue buffers 0 and 1 (n packed rows each).
 static __device__ __align__(256) unsigned char scratch[kNaBytes];
 
 static_assert(kNaBytes <= BFS_NOALLOC_SCRATCH_BYTES, "scratch larger than documented");
@@ -150,8 +150,8 @@ extern "C" bfs_status bfs_run_noalloc(const bfs_graph *g, int64_t source, int32_
   v.live_end = g->n_global;
   char *b = (char *)base;
   v.ctl = (Ctl *)b;
-  v.q0[0] = (int32_t *)(b + kNaCtlBytes);
-  v.q0[1] = (int32_t *)(b + kNaCtlBytes + kNaQueueBytes);
+  v.qr0[0] = (uint64_t *)(b + kNaCtlBytes);
+  v.qr0[1] = (uint64_t *)(b + kNaCtlBytes + kNaQueueBytes);
   hipLaunchKernelGGL(k_na_clear, dim3(1), dim3(64), 0, s, v.ctl);
   hipError_t e = hipGetLastError();
   const int grid = (int)std::min<int64_t>(std::max<int64_t>((v.n + 255) / 256, 1), 1024);
