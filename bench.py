@@ -1021,9 +1021,25 @@ def summarize_trace(args):
 
     d, log, out_name, command = args.summarize_trace
     line = _bench_line(log)
-    roof = line["roofline"]
-    kname, timed = roof["kernel"], roof.get("launches", 0)
+    roof = line.get("roofline")
     rows = list(csv.DictReader(open(os.path.join(d, "run_kernel_stats.csv"))))
+    if roof is None:
+        # no roofline kernel (e.g. the batched engine's per-level workload):
+        # the kernel table and the line's own figures only
+        md = [f"# rocprofv3 kernel trace: {line['config']['workload']}", "",
+              "Command (from the repository root):", "", "```", command, "```", "",
+              f"bench.py line: value {line['value']} {line['unit']}", "",
+              "```", json.dumps({k: line[k] for k in line if k not in ('config',)}, indent=1)[:3000], "```",
+              "", "| kernel | calls | total ms | average us | share % |", "|---|---|---|---|---|"]
+        for r in rows[:12]:
+            md.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.2f} | "
+                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+        os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+        with open(os.path.join(ROOT, "profiles", out_name), "w") as f:
+            f.write("\n".join(md) + "\n")
+        print("\n".join(md))
+        return
+    kname, timed = roof["kernel"], roof.get("launches", 0)
     kname = _dense_series(kname)
     members = set(kname.split("+"))
     sel = []
