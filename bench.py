@@ -149,7 +149,7 @@ def headline_sources(g, count):
 
 
 # Settings of the scale-24 headline plan (see run_single).
-HEADLINE_PLAN = dict(loop_mode=1, small_bin=8, wave_bin=15, chunk_edges=1024, hot_words=20352,
+HEADLINE_PLAN = dict(loop_mode=3, small_bin=7, wave_bin=13, chunk_edges=1024, hot_words=20352,
                      sparse_div=-1, relabel=1, autotune=-1)
 
 
@@ -162,14 +162,11 @@ def run_single(args, name, scale, ef):
     log(f"generated {name}: n={g.n} m={g.m} in {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
     dg = pkg.DeviceGraph.from_csr(g, dev)
-    # The scale-24 line runs the host-driven loop: it launches each level's
-    # expansion by itself, so every launch of the dominant kernel is timed with
-    # HIP events on the plan's stream. Its settings are pinned to the ones the
-    # plan autotuner reaches on this graph without a profiler attached (a
-    # profiler slows every launch and moves the tuner's choices), so profiles
-    # of this command time the same kernels. A fully autotuned plan (which may
-    # pick the captured-graph loop, timed only whole) runs first and is
-    # reported in the line's detail.
+    # The scale-24 line runs the captured level loop: 8 level steps per graph
+    # replay (the device decides each level's form and the end of the
+    # traversal), one host round trip per replay. Its settings are pinned (a profiler slows every launch and moves the plan
+    # autotuner's choices), so profiles of this command time the same kernels.
+    # A fully autotuned plan runs first and is reported in the line's detail.
     opts = dict(loop_mode=args.loop_mode, grid_blocks=args.grid_blocks, small_bin=args.small_bin,
                 wave_bin=args.wave_bin, chunk_edges=args.chunk_edges, relabel=args.relabel,
                 autotune=args.autotune, hot_words=args.hot_words, sparse_div=args.sparse_div,
@@ -219,6 +216,21 @@ def run_single(args, name, scale, ef):
     tuning = plan.tuning(0)
     exact, mismatches = oracle_check_single(plan, g, srcs[args.warmup], dist)
     log(f"oracle check of source {int(srcs[args.warmup])}: exact={exact}")
+    roof_stats, roof_note = stats, None
+    if tuning["loop_mode"] == 3 and tuning["direction"] == 0:
+        # The captured loop replays its level steps as one graph, inside which
+        # no HIP event can bracket a kernel. Its kernels are timed on a second
+        # pass over the same timed sources by a plan with the same settings
+        # that launches the same level steps directly (BFS_LOOP_ENQUEUE), each
+        # launch bracketed by HIP events on the plan's stream.
+        rplan = pkg.Plan([dg], **{**opts, "loop_mode": 5})
+        for s in srcs[:args.warmup]:
+            rplan.run(0, int(s), dist=dist)
+        roof_stats = [rplan.run(0, int(s), dist=dist)[2] for s in srcs[args.warmup:]]
+        rplan.close()
+        roof_note = ("kernel timed with HIP events on a second pass over the same timed sources, "
+                     "the same level steps launched directly (loop 5) by a plan with the same "
+                     "settings; the value's pass replays them as a captured graph")
     if tuning["direction"] == 1:
         # direction-optimizing: the dominant kernel is the bottom-up step.
         # Per launch it reads two int64 row offsets per unvisited vertex it
@@ -233,17 +245,23 @@ def run_single(args, name, scale, ef):
         per_launch_bytes = float(np.sum(k_bytes) / max(np.sum(launches), 1))
         avg_launch_ms = float(np.sum(bu_ms) / max(np.sum(launches), 1))
         n_launches = int(np.sum(launches))
-    elif tuning["loop_mode"] == 1:
-        # host-driven loop: the dominant kernel is the dense expansion
-        # (k_expand). Per launch it reads the column index of every edge it
-        # scans (4 B) and two int64 row offsets per frontier vertex (16 B);
-        # the device counts both, and each launch is timed with HIP events on
-        # the plan's stream. Queue-only levels (small frontiers) run another
-        # kernel and are not part of this figure.
-        kname = "k_expand+k_expand_wide" if tuning["hot_words"] > 4096 else "k_expand"
-        exp_ms = np.array([s.expand_ms for s in stats])
-        launches = np.array([s.expand_launches for s in stats])
-        k_bytes = np.array([4.0 * s.dense_edges + 16.0 * s.dense_frontier for s in stats])
+    elif tuning["loop_mode"] in (1, 3, 5):
+        # host-driven loop or enqueued level steps: the dominant kernel is the
+        # dense expansion (k_expand / k_expand_wide, or the level steps'
+        # k_expand_g / k_expand_gw). Per launch it reads the column index of
+        # every edge it scans (4 B) and two int64 row offsets per frontier
+        # vertex (16 B); the device counts both, and each launch is timed with
+        # HIP events on the plan's stream (for the level steps, launches also
+        # count the steps of the last round trip that find the traversal
+        # finished). Queue-only levels (small frontiers) run another kernel
+        # and are not part of this figure.
+        if tuning["loop_mode"] in (3, 5):
+            kname = "k_expand_gw" if tuning["hot_words"] > 4096 else "k_expand_g"
+        else:
+            kname = "k_expand+k_expand_wide" if tuning["hot_words"] > 4096 else "k_expand"
+        exp_ms = np.array([s.expand_ms for s in roof_stats])
+        launches = np.array([s.expand_launches for s in roof_stats])
+        k_bytes = np.array([4.0 * s.dense_edges + 16.0 * s.dense_frontier for s in roof_stats])
         achieved = float(np.sum(k_bytes) / (np.sum(exp_ms) * 1e-3) / 1e9)
         per_launch_bytes = float(np.sum(k_bytes) / max(np.sum(launches), 1))
         avg_launch_ms = float(np.sum(exp_ms) / max(np.sum(launches), 1))
@@ -253,7 +271,6 @@ def run_single(args, name, scale, ef):
         # graph, the replayed level steps), which also writes each reached
         # vertex's distance (4 B)
         kname = {2: "k_persistent_occ8" if tuning["persist_variant"] == 1 else "k_persistent",
-                 3: "k_expand_g+k_merge_g (captured level steps)",
                  4: "k_bfs_cu"}.get(tuning["loop_mode"], "unknown")
         k_bytes = 4 * edges + 16 * reached + 4 * reached
         achieved = float(np.mean(k_bytes) / (np.mean(loop_ms) * 1e-3) / 1e9)
@@ -290,6 +307,7 @@ def run_single(args, name, scale, ef):
                      "bytes_per_launch": int(per_launch_bytes),
                      "avg_launch_ms": round(avg_launch_ms, 4), "launches": n_launches,
                      "traffic_detail": traffic},
+        **({"roofline_timing": roof_note} if roof_note else {}),
         "detail": {
             "gteps_trimmed_mean_time": round(metrics.gteps(np.mean(edges), metrics.trimmed_mean(ms) * 1e-3), 3),
             "gteps_whole_graph_convention": round(metrics.harmonic_mean(g.m / (ms * 1e-3) / 1e9), 3),
@@ -303,6 +321,9 @@ def run_single(args, name, scale, ef):
     }
     if auto_line is not None:
         out["detail"]["autotuned_loop"] = auto_line
+    copy_gbs = measured_copy_gbs()
+    out["roofline"]["measured_copy_gbs"] = copy_gbs
+    out["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_single(g, srcs[args.warmup:], budget_s=args.cpu_budget)
     plan.close()
@@ -917,6 +938,10 @@ def run_share29(args):
     }
     plan.close()
     plan_do.close()
+    copy_gbs = measured_copy_gbs()
+    for key in ("roofline", "roofline_expansion"):
+        out[key]["measured_copy_gbs"] = copy_gbs
+        out[key]["frac_of_copy"] = round(out[key]["achieved"] / copy_gbs, 4)
     return out
 
 
@@ -1048,7 +1073,11 @@ def summarize_trace(args):
             if _short(r["Kernel_Name"]) in members:
                 sel.append((int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
     sel.sort()
+    prev = []
     if timed:
+        # a line whose kernel was timed on a second pass: the pass before it
+        # (the value's captured-graph replays) launched as many of the kernel
+        prev = sel[-2 * timed:-timed] if line.get("roofline_timing") else []
         sel = sel[-timed:]
     avg_ms = sum(x for _, x in sel) / max(len(sel), 1) / 1e6
     md = [f"# rocprofv3 kernel trace: {line['config']['workload']}", "",
@@ -1060,6 +1089,9 @@ def summarize_trace(args):
           f"bench.py); roofline achieved {roof['achieved']} {roof['unit']} "
           f"({roof['frac']} of {roof['peak']}), {roof['bytes_per_launch']} algorithmic bytes "
           f"per launch.", "",
+          *([f"The same kernel's {len(prev)} dispatches of the value's pass (level steps replayed "
+             f"as a captured graph) average {sum(x for _, x in prev) / len(prev) / 1e6:.4f} ms.", ""]
+            if prev else []),
           "Whole run (plan creation and autotuning included):", "",
           "| kernel | calls | total ms | average us | share % |", "|---|---|---|---|---|"]
     for r in rows[:12]:
@@ -1112,6 +1144,27 @@ def summarize_counters(args):
     with open(os.path.join(ROOT, "profiles", out_name), "w") as f:
         f.write("\n".join(md) + "\n")
     print("\n".join(md))
+
+
+def measured_copy_gbs(nbytes=1 << 30, reps=5):
+    """HBM rate of a plain device-to-device copy (bytes read + bytes written
+    per second), timed with HIP events: the practical ceiling that a
+    streaming kernel reaches on this device, reported beside the nominal
+    peak."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return round(2.0 * nbytes / (ms * 1e-3) / 1e9, 1)
 
 
 def copy_probe(nbytes):

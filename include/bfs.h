@@ -92,6 +92,10 @@ typedef int32_t (*bfs_exchange_fn)(void *ctx, int32_t level, const uint64_t *loc
 #define BFS_LOOP_CU 4         /* whole traversal in one workgroup with its bitmaps in LDS: whole
                                  graphs with m < 2^25 whose two n-bit bitmaps fit in one
                                  workgroup's LDS (else BFS_ERR_ARG when asked for explicitly) */
+#define BFS_LOOP_ENQUEUE 5    /* the captured loop's level steps (the device decides each level's
+                                 form and the end of the traversal) launched directly, 8 steps
+                                 per host round trip, each launch bracketed by HIP events on
+                                 the plan's stream: per-level device times without a graph */
 
 typedef struct {
   void *hip_stream;        /* hipStream_t; NULL = the null stream */
@@ -170,8 +174,10 @@ typedef struct {
   float loop_ms;         /* device time of the level loop alone (the persistent launch, or
                             first expansion to last merge when host-driven) */
   float expand_ms;       /* host-driven loop: summed device time of the dense expansion
-                            launches (k_expand) of the first 64 levels (0 for the other
-                            loops) */
+                            launches (k_expand) of the first 64 levels; BFS_LOOP_ENQUEUE:
+                            of the first 64 expansion steps it launched (8 per round trip,
+                            counting the steps that found the traversal already finished;
+                            their kernels return at once); 0 for the other loops */
   float merge_ms;        /* the same for the merge launches */
   int32_t expand_launches; /* launches summed in expand_ms */
   int64_t dense_edges;     /* edges scanned by the dense (bitmap) expansions of this traversal,
@@ -337,8 +343,9 @@ bfs_status bfs_level_stats(bfs_plan_t p, int64_t *frontier, int64_t *hist, int32
                            int32_t *levels);
 
 /*
- * Per-level device times of the last bfs_run when it drove the host loop
- * (HIP events around each launch, first BFS_MAX_TIMED_LEVELS levels):
+ * Per-level device times of the last bfs_run when it drove the host loop or
+ * the enqueued level steps (BFS_LOOP_ENQUEUE) (HIP events around each
+ * launch, first BFS_MAX_TIMED_LEVELS levels):
  * expand_ms[L] = Phase 1 of level L (the top-down expansion, the queue-only
  * level or the bottom-up step), merge_ms[L] = its Phase 2 merge (0 for a
  * queue-only level, which has none), kind[L] = 0 top-down with a bitmap

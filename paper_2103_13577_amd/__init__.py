@@ -20,7 +20,7 @@ BFS_OK = 0
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_WORKSPACE", 3: "ERR_HIP", 4: "ERR_DEPTH",
                 5: "ERR_CAPACITY", 6: "ERR_EXCHANGE", 7: "ERR_STATE", 8: "ERR_TIMEOUT",
                 9: "ERR_DEVICE"}
-LOOP_AUTO, LOOP_HOST, LOOP_PERSISTENT, LOOP_GRAPH, LOOP_CU = 0, 1, 2, 3, 4
+LOOP_AUTO, LOOP_HOST, LOOP_PERSISTENT, LOOP_GRAPH, LOOP_CU, LOOP_ENQUEUE = 0, 1, 2, 3, 4, 5
 DIR_TOPDOWN, DIR_OPTIMIZING = 0, 1
 OUT_U8, OUT_I32 = 0, 1
 BATCH_ONE_LAUNCH, BATCH_STREAMING = 1, 2
@@ -408,8 +408,8 @@ class Plan:
         return f[:nl.value].copy(), h[:nl.value].copy()
 
     def level_times(self):
-        """(Phase 1 ms, Phase 2 ms, kind) per level of the last host-driven
-        traversal (kind 0 top-down, 1 queue-only, 2 bottom-up)."""
+        """(Phase 1 ms, Phase 2 ms, kind) per level of the last host-driven or
+        enqueued-step traversal (kind 0 top-down, 1 queue-only, 2 bottom-up)."""
         n = 64
         a = np.zeros(n, dtype=np.float32)
         b = np.zeros(n, dtype=np.float32)

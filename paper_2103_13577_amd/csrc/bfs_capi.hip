@@ -234,7 +234,7 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
     delete p;
     return BFS_ERR_ARG;
   }
-  if (o->loop_mode < BFS_LOOP_AUTO || o->loop_mode > BFS_LOOP_CU) {
+  if (o->loop_mode < BFS_LOOP_AUTO || o->loop_mode > BFS_LOOP_ENQUEUE) {
     g_create_error = "unknown loop_mode";
     delete p;
     return BFS_ERR_ARG;
@@ -797,6 +797,38 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
     if (c.err) return p->fail(BFS_ERR_DEVICE, "level limit exceeded");
     p->persistent_levels = c.levels;
     p->level = c.levels;
+  } else if (mode == BFS_LOOP_ENQUEUE) {
+    // the captured loop's steps launched directly: the host enqueues
+    // kGraphLevels steps (with the first kTimedLevels steps' events), then
+    // reads the control block once
+    s = into_visited(p, graph, dist);
+    if (s) return s;
+    View v = p->view(graph, nullptr);  // the kernels take the distance array from the control block
+    const int max_levels = (int)std::min<int64_t>(g.n_global + 1, 1ll << 30);
+    const int hot = p->cur_relabel ? tu.hot_words : 0;
+    const int egrid = p->expand_grid(hot), mgrid = p->merge_grid(v.words);
+    const int64_t max_rounds = g.n_global / Plan::kGraphLevels + 2;
+    e = hipEventRecord(p->ev[2], p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
+    Ctl c;
+    int steps = 0;
+    for (int64_t i = 0;; ++i) {
+      const bool timed = steps + Plan::kGraphLevels <= Plan::kTimedLevels;
+      e = enqueue_graph_levels(v, Plan::kGraphLevels, max_levels, egrid, mgrid, hot, p->stream,
+                               timed ? p->lev + steps : nullptr);
+      if (e != hipSuccess) return p->hip_fail(e, "level step launch");
+      if (timed) steps += Plan::kGraphLevels;
+      s = p->read_ctl(c);
+      if (s) return s;
+      if (c.gdone) break;
+      if (i + 1 >= max_rounds) return p->fail(BFS_ERR_DEVICE, "level limit exceeded");
+    }
+    e = hipEventRecord(ev1, p->stream);
+    if (e != hipSuccess) return p->hip_fail(e, "hipEventRecord");
+    if (c.err) return p->fail(BFS_ERR_DEVICE, "level limit exceeded");
+    p->persistent_levels = c.levels;
+    p->level = c.levels;
+    p->enqueued_steps = steps;
   } else if (!host_loop) {
     s = into_visited(p, graph, dist);
     if (s) return s;
@@ -893,6 +925,24 @@ bfs_status bfs_run(bfs_plan_t p, int32_t graph, int64_t source, int32_t *dist, i
   p->last_expand_ms = p->last_merge_ms = p->last_queue_ms = p->last_bu_ms = 0.f;
   p->last_expand_launches = 0;
   p->timed_levels = 0;
+  if (mode == BFS_LOOP_ENQUEUE) {
+    // every timed step counts as an expansion launch, also the steps of the
+    // last round that found the traversal finished (their kernels return at
+    // once), so the totals cover every timed dispatch; per-level times stop
+    // at the last level
+    for (int L = 0; L < p->enqueued_steps; ++L) {
+      float a = 0.f, b = 0.f;
+      if (hipEventElapsedTime(&a, p->lev[L][0], p->lev[L][1]) != hipSuccess) a = 0.f;
+      if (hipEventElapsedTime(&b, p->lev[L][1], p->lev[L][2]) != hipSuccess) b = 0.f;
+      p->last_expand_ms += a;
+      p->last_merge_ms += b;
+      p->last_expand_launches += 1;
+      p->lev_ms[L][0] = a;
+      p->lev_ms[L][1] = b;
+      p->level_kind[L] = 0;
+    }
+    p->timed_levels = std::min(p->enqueued_steps, p->level);
+  }
   if (host_loop) {
     const int nl = std::min(p->level, Plan::kTimedLevels);
     p->timed_levels = nl;

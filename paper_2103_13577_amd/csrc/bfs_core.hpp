@@ -40,6 +40,8 @@ struct Ctl {
   int32_t glevel;         // graph-launched loop: level the next captured step runs
   int32_t gdone;          // graph-launched loop: traversal finished
   int32_t *gdist;         // graph-launched loop: caller's distance array
+  uint64_t gedges[2];     // graph-launched loop: `edges` after the merges of the last two
+                          // levels ([1] newer; the current frontier's edges are the difference)
   uint64_t xedges;        // edges scanned by dense (bitmap) expansions
   uint64_t xfront;        // frontier vertices of dense expansions
   uint64_t buedges;       // adjacency entries examined by bottom-up steps
@@ -138,9 +140,11 @@ hipError_t launch_clear_stats_row(const View &v, int level, hipStream_t s);
 hipError_t launch_parent(const View &v, int32_t *parent, int64_t src, int grid, hipStream_t s);
 hipError_t launch_persistent(const View &v, int max_levels, int grid, int variant, hipStream_t s);
 // Enqueues `levels` graph-launched level steps (expand, merge, advance) on s;
-// used while capturing a hipGraph.
+// used while capturing a hipGraph. ev (NULL: none) holds three events per
+// step, recorded before its expansion, after it and after its merge.
 hipError_t enqueue_graph_levels(const View &v, int levels, int max_levels, int expand_grid,
-                                int merge_grid, uint32_t hot_words, hipStream_t s);
+                                int merge_grid, uint32_t hot_words, hipStream_t s,
+                                hipEvent_t (*ev)[3] = nullptr);
 int persistent_blocks_per_cu(int variant);
 int expand_blocks_per_cu(uint32_t hot_words);
 hipError_t launch_bottom_up(const View &v, int level, int grid, uint32_t hot_words, const uint64_t *front,

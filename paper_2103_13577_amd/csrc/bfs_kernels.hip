@@ -81,6 +81,8 @@ __global__ void __launch_bounds__(kBlock) k_reset(View v, int64_t src_caller) {
       }
       c->edges = (uint64_t)deg;
     }
+    c->gedges[0] = 0;
+    c->gedges[1] = c->edges;
     if (v.stats) {
       v.lvl_frontier[0] = owned ? 1 : 0;
       for (int b = 0; b < 2 * kNumBins; ++b) v.lvl_hist[b] = 0;  // rows 0 and 1
@@ -1182,16 +1184,18 @@ __device__ __forceinline__ void expand_g_body(const View &v, uint32_t hot_words)
     expand_phase<true, BLOCK>(v, dist, L, blockIdx.x, gridDim.x);
     return;
   }
-  // the LDS copy of the hub bits pays off only when the frontier is large
-  const int cur = L % kRing;
-  const uint64_t fsize = (uint64_t)load_relaxed32(&v.ctl->qn[cur][0]) +
-                         load_relaxed32(&v.ctl->qn[cur][1]) +
-                         (load_relaxed64(&v.ctl->heavy[cur]) >> kHeavyShift);
-  if (hot_words && fsize * 16 >= (uint64_t)v.n)
-    expand_phase<false, BLOCK>(v, dist, L, blockIdx.x, gridDim.x,
-                               load_hot<BLOCK>(v, s_hot, hot_words));
+  // the LDS copy of the hub bits pays off only when the frontier's edges
+  // are at least the vertex count (the host-driven loop's rule)
+  const uint64_t fedges = load_relaxed64(&v.ctl->gedges[1]) - load_relaxed64(&v.ctl->gedges[0]);
+  // the 1024-thread variant runs one block per CU, which leaves each
+  // wavefront the registers for twice the edges per lane in flight
+  constexpr int KU = BLOCK == kWideBlock ? 2 * kUnroll : kUnroll;
+  constexpr int KS = BLOCK == kWideBlock ? 2 * kUnrollSmall : kUnrollSmall;
+  if (hot_words && fedges >= (uint64_t)v.n)
+    expand_phase<false, BLOCK, KU, KS>(v, dist, L, blockIdx.x, gridDim.x,
+                                       load_hot<BLOCK>(v, s_hot, hot_words));
   else
-    expand_phase<false, BLOCK>(v, dist, L, blockIdx.x, gridDim.x);
+    expand_phase<false, BLOCK, KU, KS>(v, dist, L, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(kBlock) k_expand_g(View v, uint32_t hot_words) {
@@ -1220,6 +1224,8 @@ __global__ void k_advance_g(View v, int max_levels) {
   if (threadIdx.x != 0 || load_relaxed_i32(&v.ctl->gdone)) return;
   const int L = v.ctl->glevel;
   const uint64_t nn = v.ctl->newcnt[L % 3];
+  v.ctl->gedges[0] = v.ctl->gedges[1];
+  v.ctl->gedges[1] = v.ctl->edges;
   if (v.stats && L + 1 < kMaxStatLevels) v.lvl_frontier[L + 1] = (int64_t)v.ctl->ownedcnt[L % 3];
   if (v.stats && L + 2 < kMaxStatLevels)
     for (int b = 0; b < kNumBins; ++b) v.lvl_hist[(L + 2) * kNumBins + b] = 0;
@@ -1233,13 +1239,19 @@ __global__ void k_advance_g(View v, int max_levels) {
 }
 
 hipError_t enqueue_graph_levels(const View &v, int levels, int max_levels, int expand_grid,
-                                int merge_grid, uint32_t hot_words, hipStream_t s) {
+                                int merge_grid, uint32_t hot_words, hipStream_t s, hipEvent_t (*ev)[3]) {
   for (int i = 0; i < levels; ++i) {
+    hipError_t e = ev ? hipEventRecord(ev[i][0], s) : hipSuccess;
+    if (e != hipSuccess) return e;
     if (hot_words > kNarrowHotMax)
       hipLaunchKernelGGL(k_expand_gw, dim3(expand_grid), dim3(kWideBlock), hot_words * 8, s, v, hot_words);
     else
       hipLaunchKernelGGL(k_expand_g, dim3(expand_grid), dim3(kBlock), hot_words * 8, s, v, hot_words);
+    e = ev ? hipEventRecord(ev[i][1], s) : hipSuccess;
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_merge_g, dim3(merge_grid), dim3(kBlock), 0, s, v);
+    e = ev ? hipEventRecord(ev[i][2], s) : hipSuccess;
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_advance_g, dim3(1), dim3(64), 0, s, v, max_levels);
   }
   return hipGetLastError();

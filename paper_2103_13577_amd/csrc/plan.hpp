@@ -84,6 +84,7 @@ struct bfs_plan_s {
   bool time_levels = false;              // set while bfs_run drives the host loop
   float lev_ms[kTimedLevels][2] = {};    // last host-driven traversal: Phase 1 / Phase 2 ms per level
   int32_t timed_levels = 0;              // levels in lev_ms (0: the last traversal was not host-driven)
+  int32_t enqueued_steps = 0;            // BFS_LOOP_ENQUEUE: level steps bracketed by lev events
   std::string err;
 
   // single-source traversal state

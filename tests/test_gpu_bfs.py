@@ -75,6 +75,11 @@ MODES = [dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST),
          # the same all-dense loops with the atomic-OR expansion instead of byte marks
          dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1, hot_words=16384, small_bin=3, wave_bin=6,
               chunk_edges=128, mark_mode=-1),
+         # the captured loop's level steps launched directly (queue-only levels
+         # and the narrow hub copy; all-dense levels with byte marks and the wide copy)
+         dict(loop_mode=pkg.LOOP_ENQUEUE, hot_words=2048),
+         dict(loop_mode=pkg.LOOP_ENQUEUE, sparse_div=-1, hot_words=16384, small_bin=3, wave_bin=6,
+              chunk_edges=128),
          dict(loop_mode=pkg.LOOP_GRAPH, sparse_div=-1, hot_words=2048, mark_mode=-1),
          dict(loop_mode=pkg.LOOP_PERSISTENT, sparse_div=-1, mark_mode=-1)]
 
@@ -141,7 +146,7 @@ def test_level_stats(gpu):
     s = int(gg.pick_sources(g, 1, seed=5)[0])
     ref = oracle.bfs(g, s)
     deg = g.degrees()
-    for mode in (pkg.LOOP_PERSISTENT, pkg.LOOP_HOST, pkg.LOOP_GRAPH, pkg.LOOP_CU):
+    for mode in (pkg.LOOP_PERSISTENT, pkg.LOOP_HOST, pkg.LOOP_GRAPH, pkg.LOOP_CU, pkg.LOOP_ENQUEUE):
         dg = pkg.DeviceGraph.from_csr(g, gpu)
         plan = pkg.Plan([dg], loop_mode=mode, collect_stats=True)
         plan.run(0, s)
@@ -799,33 +804,40 @@ def rmat24(gpu):
 
 
 def test_headline_plan_rmat24(gpu, rmat24):
-    """Exactly what the benchmark times: its pinned headline plan (host-driven
-    loop, the 1024-thread expansion with a 16K-word LDS hub copy against a
-    262,144-word bitmap, every level dense, byte marks) on its graph, from two
-    of its timed sources (indices 3 and 4 of its seeded source sequence, timed
-    under the default warm-up of 3): whole distance arrays bit-exact against
-    the oracle, and the canonical parents of one source."""
+    """Exactly what the benchmark times: its pinned headline plan (captured
+    level loop, 8 steps per replay, the 1024-thread expansion with a
+    20,352-word LDS hub copy against a 262,144-word bitmap, every level dense,
+    byte marks) and the plan that times its kernels (the same settings, level
+    steps launched directly), on its graph, from two of its timed sources
+    (indices 3 and 4 of its seeded source sequence, timed under the default
+    warm-up of 3): whole distance arrays bit-exact against the oracle, and the
+    canonical parents of one source."""
     import torch
     import bench
     g, dg, ref = rmat24
-    plan = pkg.Plan([dg], **bench.HEADLINE_PLAN)
-    t = plan.tuning(0)
-    assert t["loop_mode"] == pkg.LOOP_HOST and t["relabelled"] == 1
-    assert 4096 < t["hot_words"] < (g.n + 63) // 64  # wide expansion; copy smaller than the bitmap
-    assert t["sparse_div"] == 0 and t["mark_mode"] == 1
     srcs = bench.headline_sources(g, 5)[3:5]
-    for i, s in enumerate(srcs):
-        print(f"[gpu] rmat24 headline plan src={s}", flush=True)
-        d, p, st = plan.run(0, int(s), parent=(i == 0))
-        torch.cuda.synchronize()
-        r = ref(int(s))
-        assert np.array_equal(d.cpu().numpy(), r)
-        if i == 0:
-            assert np.array_equal(p.cpu().numpy(), oracle.parent(g, r))
-        assert st.edges_scanned == oracle.edges_scanned(g, r)
-        assert st.expand_launches == st.levels  # every level ran the dense expansion
-        assert st.dense_edges == st.edges_scanned
-    plan.close()
+    for loop in (bench.HEADLINE_PLAN["loop_mode"], pkg.LOOP_ENQUEUE):
+        plan = pkg.Plan([dg], **{**bench.HEADLINE_PLAN, "loop_mode": loop})
+        t = plan.tuning(0)
+        assert t["loop_mode"] == loop and t["relabelled"] == 1
+        assert 4096 < t["hot_words"] < (g.n + 63) // 64  # wide expansion; copy smaller than the bitmap
+        assert t["sparse_div"] == 0 and t["mark_mode"] == 1
+        for i, s in enumerate(srcs):
+            print(f"[gpu] rmat24 headline plan loop={loop} src={s}", flush=True)
+            d, p, st = plan.run(0, int(s), parent=(i == 0))
+            torch.cuda.synchronize()
+            r = ref(int(s))
+            assert np.array_equal(d.cpu().numpy(), r)
+            if i == 0:
+                assert np.array_equal(p.cpu().numpy(), oracle.parent(g, r))
+            assert st.edges_scanned == oracle.edges_scanned(g, r)
+            assert st.dense_edges == st.edges_scanned  # every level ran the dense expansion
+            if loop == pkg.LOOP_ENQUEUE:
+                # all 8 steps of each round trip are timed
+                assert st.expand_launches == -(-st.levels // 8) * 8
+                a, b, kind = plan.level_times()
+                assert len(a) == st.levels and (a > 0).all() and (b > 0).all() and (kind == 0).all()
+        plan.close()
 
 
 FULL_SIZE_PLANS = [dict(loop_mode=pkg.LOOP_HOST, autotune=-1),
@@ -833,7 +845,9 @@ FULL_SIZE_PLANS = [dict(loop_mode=pkg.LOOP_HOST, autotune=-1),
                    dict(loop_mode=pkg.LOOP_PERSISTENT, autotune=-1),
                    dict(loop_mode=pkg.LOOP_GRAPH, autotune=-1, sparse_div=-1, hot_words=16384),
                    dict(loop_mode=pkg.LOOP_HOST, autotune=-1, sparse_div=-1, hot_words=16384,
-                        small_bin=8, wave_bin=15, chunk_edges=1024, mark_mode=-1)]
+                        small_bin=8, wave_bin=15, chunk_edges=1024, mark_mode=-1),
+                   dict(loop_mode=pkg.LOOP_HOST, autotune=-1, sparse_div=-1, hot_words=20352,
+                        small_bin=6, wave_bin=14, chunk_edges=2048)]
 
 
 @pytest.mark.parametrize("plan_opts", FULL_SIZE_PLANS, ids=[str(i) for i in range(len(FULL_SIZE_PLANS))])
@@ -880,6 +894,7 @@ def test_graph_replays_match_eager(gpu):
 
 
 NO_ALLOC_PLANS = [dict(loop_mode=pkg.LOOP_HOST), dict(loop_mode=pkg.LOOP_GRAPH),
+                  dict(loop_mode=pkg.LOOP_ENQUEUE, sparse_div=-1, hot_words=8192),
                   dict(loop_mode=pkg.LOOP_GRAPH, sparse_div=-1, hot_words=2048),
                   dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1),
                   dict(loop_mode=pkg.LOOP_CU), dict()]
