@@ -1002,7 +1002,7 @@ def summarize_pmc(args):
         out, cnt = {}, {}
         for k, per in vals.items():
             ids = sorted(per)
-            if last and k in (group, "k_merge"):
+            if last and k in (group, "k_merge", "k_merge_g"):
                 ids = ids[-last:]
             out[k] = sum(per[i] for i in ids) / len(ids)
             cnt[k] = len(ids)
@@ -1015,7 +1015,7 @@ def summarize_pmc(args):
     copy_kib = args.copy_bytes / 1024.0
     ck = [k for k in cf if "copy" in k.lower()][0]
     fscale, wscale = copy_kib / cf[ck], copy_kib / cw[ck]
-    out = {"workload": "R-MAT scale 24 edge factor 16, host-driven level loop",
+    out = {"workload": "R-MAT scale 24 edge factor 16, " + line["config"]["workload"].split(", ")[-1],
            "plan": line["config"].get("plan"),
            "commands": args.pmc_commands,
            "kernel_source_hash": kernel_source_hash(),
@@ -1023,7 +1023,7 @@ def summarize_pmc(args):
                           "fetch_scale": fscale, "write_scale": wscale},
            "kernels": {}}
     for k in fetch:
-        if k not in (group, "k_merge", "k_reset"):
+        if k not in (group, "k_merge", "k_merge_g", "k_reset"):
             continue
         fb = fetch[k] * fscale * 1024
         wb = write.get(k, 0.0) * wscale * 1024
