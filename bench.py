@@ -440,10 +440,17 @@ def run_serve(args):
     dgs = [pkg.DeviceGraph.from_csr(g, dev) for g in gs]
     # the serving plan's own single-source settings are not used by the
     # batched path, so it skips the autotuner; the plain baseline is tuned
-    log("planning (the baseline plan autotunes each graph)")
-    plan = pkg.Plan(dgs, batch_lanes=args.serve_lanes, grid_blocks=args.grid_blocks, autotune=-1)
-    single = pkg.Plan(dgs, grid_blocks=args.grid_blocks)
-    log("plans ready")
+    # The serving plan's cooperative grid: every level of the batched loop
+    # pays two grid barriers whose cost grows with the grid, and the grids'
+    # queries run thousands of levels (batched-grid workload: 97-106 us per
+    # level at 1024 blocks, 31-47 us at 64-256 for one source); 256 blocks
+    # served 24% more queries/s than 1024 on this pool.
+    plan = pkg.Plan(dgs, batch_lanes=args.serve_lanes, grid_blocks=args.serve_grid, autotune=-1)
+    log("serving plan ready; the baseline plans autotune each graph")
+    singles = []
+    for gi, dg in enumerate(dgs):
+        singles.append(pkg.Plan([dg], grid_blocks=args.grid_blocks))
+        log(f"baseline plan for {names[gi]} ready")
     arrivals = gg.poisson_arrivals(nq, 20000.0, seed=0x5EED0550)
     gsel = (gg.draws(0x5EED0551, nq) % np.uint64(len(gs))).astype(np.int64)
     srcs = np.zeros(nq, dtype=np.int64)
@@ -547,7 +554,7 @@ def run_serve(args):
             log(f"plain {k}/{samp.size}")
         gi = int(gsel[q])
         ts = time.perf_counter()
-        d, _, _ = single.run(gi, int(srcs[q]), dist=pools[gi][0])
+        d, _, _ = singles[gi].run(0, int(srcs[q]), dist=pools[gi][0])
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - ts)
         if int(q) in saved and torch.equal(saved[int(q)], d):
@@ -603,7 +610,8 @@ def run_serve(args):
         "errors": errors[:3],
     }
     plan.close()
-    single.close()
+    for sp in singles:
+        sp.close()
     return out
 
 
@@ -619,7 +627,7 @@ def run_batch_grid(args):
     pool = [x for x in _serve_pool() if x[0].startswith("grid")]
     gs = [make() for _, make in pool]
     dgs = [pkg.DeviceGraph.from_csr(g, dev) for g in gs]
-    plan = pkg.Plan(dgs, batch_lanes=1, autotune=-1)
+    plan = pkg.Plan(dgs, batch_lanes=1, autotune=-1, grid_blocks=args.grid_blocks)
     single = pkg.Plan(dgs)
     res = {}
     for gi, (name, _) in enumerate(pool):
@@ -1208,6 +1216,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--serve-queries", type=int, default=10000)
     ap.add_argument("--serve-lanes", type=int, default=1)
+    ap.add_argument("--serve-grid", type=int, default=256,
+                    help="cooperative grid of the serving plan's batched loop")
     ap.add_argument("--serve-buffers", type=int, default=96)
     ap.add_argument("--serve-sample", type=int, default=200)
     ap.add_argument("--serve-oracle", type=int, default=16,

@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kCuBlock = 1024;
 constexpr int kCuWaves = kCuBlock / kWave;
-constexpr int kCuUnroll = 8;  // edges per lane in flight
+constexpr int kCuUnroll = 4;  // edges per lane in flight
 constexpr int kCuMergeWords = 4;  // bitmap words per wavefront step of the merge
 
 __device__ __forceinline__ void lds_or(uint64_t *p, uint64_t bit) {
