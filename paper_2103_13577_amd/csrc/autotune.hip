@@ -140,7 +140,7 @@ bfs_status tune_graph(Plan *p, size_t gi) {
       for (int var = 0; var < 2; ++var) {
         const int bpc = p->bpc[var];
         if (bpc <= 0) continue;
-        const int cap = std::min(bpc * p->num_cus, kBarrierGroup * kBarrierMaxGroups);
+        const int cap = std::min(bpc * p->num_cus, kBarrierMaxBlocks);
         int last = -1;
         for (int grid : {cap, (bpc / 2) * p->num_cus, p->num_cus, p->num_cus / 4, 32, 8}) {
           grid = std::min(grid, cap);

@@ -239,7 +239,7 @@ bfs_status bfs_plan_create(const bfs_graph *graphs, int32_t ngraphs, const bfs_o
     delete p;
     return BFS_ERR_ARG;
   }
-  if (o->grid_blocks > kBarrierGroup * kBarrierMaxGroups) {
+  if (o->grid_blocks > kBarrierMaxBlocks) {
     g_create_error = "grid_blocks above the grid barrier's limit of 2048";
     delete p;
     return BFS_ERR_ARG;

@@ -41,10 +41,12 @@ __global__ void __launch_bounds__(kBlock) k_reset(View v, int64_t src_caller) {
     v.visited[i] = (i == sw) ? (1ull << (src & 63)) : 0ull;
     v.next[i] = 0ull;
   }
-  if (blockIdx.x == 0 && threadIdx.x < kBarrierMaxGroups) v.ctl->bar.group[threadIdx.x].count = 0;
+  // the grid barrier starts from barrier 0 (every announcement 0)
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < kBarrierMaxBlocks; i += blockDim.x) v.ctl->bar.arrive[i] = 0;
   if (tid == 0) {
     Ctl *c = v.ctl;
-    c->bar.top = 0;
+    c->bar.gen = 0;
     c->bar.tripped = 0;
     for (int r = 0; r < kRing; ++r) {
       c->qn[r][0] = c->qn[r][1] = 0;

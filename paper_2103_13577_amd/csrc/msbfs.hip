@@ -202,7 +202,7 @@ bfs_status batch_autotune(Plan *p, BatchState *b, int bpc) {
   float best_ms = 1e30f;
   auto trial = [&](const Setting &c) -> bfs_status {
     if (c.small_bin < 1 || c.wave_bin < c.small_bin || c.grid <= 0 || c.grid > bpc * p->num_cus ||
-        c.grid > kBarrierGroup * kBarrierMaxGroups)
+        c.grid > kBarrierMaxBlocks)
       return BFS_OK;
     apply(c);
     float warm = 0.f, ms = 0.f;
@@ -340,7 +340,7 @@ bfs_status batch_init(Plan *p) {
   }
   int bpc = ms_blocks_per_cu(lw);
   b->grid = p->opt.grid_blocks > 0 ? p->opt.grid_blocks : p->num_cus * std::min(std::max(bpc, 1), 4);
-  if (b->grid > kBarrierGroup * kBarrierMaxGroups) {
+  if (b->grid > kBarrierMaxBlocks) {
     (void)hipHostFree(b->h_adm);
     (void)hipHostFree(b->h_mask);
     delete b;

@@ -163,7 +163,7 @@ bfs_status choose_tuning(Plan *p) {
     t.persist_variant = p->bpc[1] > 0 ? 1 : 0;
     const int per_cu = std::min(p->bpc[t.persist_variant], 8);
     const int64_t work_grid = (m + (p->graphs[i].v_end - p->graphs[i].v_begin) + (1 << 14) - 1) >> 14;
-    const int64_t max_grid = std::min(per_cu * p->num_cus, kBarrierGroup * kBarrierMaxGroups);
+    const int64_t max_grid = std::min(per_cu * p->num_cus, kBarrierMaxBlocks);
     t.persist_grid = (int)std::max<int64_t>(1, std::min<int64_t>(max_grid, std::max<int64_t>(work_grid, 16)));
     t.loop_mode = (p->coop && per_cu > 0) ? BFS_LOOP_PERSISTENT : BFS_LOOP_HOST;
     // small whole graphs (up to 2^20 edges): one workgroup with the bitmaps
