@@ -93,6 +93,20 @@ def measured_traffic(kernel, per_launch_bytes):
             "source": "profiles/traffic_rmat24.json"}
 
 
+def measured_share_traffic():
+    """HBM bytes of the partitioned share's timed top-down traversals from the
+    committed rocprofv3 --pmc summary (k_merge per launch, k_expand per
+    traversal), or None when it was taken on other kernel sources."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic_share29.json")) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("kernels")
+
+
 def pinned_core():
     """The first core this process may run on (Linux), or None."""
     try:
@@ -760,6 +774,7 @@ def run_share29(args):
             out.append((w[:, None] * 64 + ar)[bits])
         return torch.cat(out).to(torch.int32) if out else torch.empty(0, dtype=torch.int32, device=dev)
 
+    forms_all = args.share_forms == "all"
     list_cap = g.n // 32
     lists = []
     for L in range(len(staged)):
@@ -816,21 +831,24 @@ def run_share29(args):
         mrg_ms = [bb.elapsed_time(c) for a, bb, c in ev]
         return exp_ms, mrg_ms, t_begin.elapsed_time(ev[-1][2]), ok, sent_lists
 
-    _, _, _, ok_l, _ = one_lists(check=True)
-    exact_lists = ok_l and np.array_equal(dist.cpu().numpy(), ref)
-    log(f"list form exact={exact_lists}")
+    if forms_all:
+        _, _, _, ok_l, _ = one_lists(check=True)
+        exact_lists = ok_l and np.array_equal(dist.cpu().numpy(), ref)
+        log(f"list form exact={exact_lists}")
 
     # Direction-optimizing: a level whose frontier holds at least n/24
     # vertices runs Phase 1 bottom-up (bfs_expand_bottom_up); its staged
     # messages are then every node's owned vertices of the next level.
     sizes = np.bincount(ref[ref >= 0], minlength=len(staged) + 2)
     bu_levels = sorted(L for L in range(len(staged)) if sizes[L] * 24 >= g.n)
-    bu_local, bu_inc = oracle.stage_bottom_up(g.n, ref, b, 0, 2, levels=set(bu_levels))
-    staged_do = [[torch.from_numpy(bu_inc[L, j].view(np.int64)).to(dev) for j in range(bu_inc.shape[1])]
-                 if L in bu_levels else staged[L] for L in range(len(staged))]
-    del bu_inc
-    log(f"direction-optimizing: bottom-up levels {bu_levels}")
-    plan_do = pkg.Plan([dg], direction=pkg.DIR_OPTIMIZING)
+    plan_do = None
+    if forms_all:
+        bu_local, bu_inc = oracle.stage_bottom_up(g.n, ref, b, 0, 2, levels=set(bu_levels))
+        staged_do = [[torch.from_numpy(bu_inc[L, j].view(np.int64)).to(dev) for j in range(bu_inc.shape[1])]
+                     if L in bu_levels else staged[L] for L in range(len(staged))]
+        del bu_inc
+        log(f"direction-optimizing: bottom-up levels {bu_levels}")
+        plan_do = pkg.Plan([dg], direction=pkg.DIR_OPTIMIZING)
 
     def one_do(check):
         ev = []
@@ -870,17 +888,19 @@ def run_share29(args):
         mrg_ms = [bb.elapsed_time(c) for a, bb, c in ev]
         return exp_ms, mrg_ms, t_begin.elapsed_time(ev[-1][2]), ok, st_do
 
-    _, _, _, ok_d, _ = one_do(check=True)
-    exact_do = ok_d and np.array_equal(dist.cpu().numpy(), ref)
-    log(f"direction-optimizing exact={exact_do}")
+    if forms_all:
+        _, _, _, ok_d, _ = one_do(check=True)
+        exact_do = ok_d and np.array_equal(dist.cpu().numpy(), ref)
+        log(f"direction-optimizing exact={exact_do}")
 
     st, _, _, _, ok = one(check=True)
     exact = ok and np.array_equal(dist.cpu().numpy(), ref)
     runs = [one(check=False) for _ in range(max(args.steps if args.steps < 64 else 3, 1))]
-    runs_l = [one_lists(check=False) for _ in range(len(runs))]
-    tot_l = np.array([r[2] for r in runs_l])
-    runs_d = [one_do(check=False) for _ in range(len(runs))]
-    tot_d = np.array([r[2] for r in runs_d])
+    if forms_all:
+        runs_l = [one_lists(check=False) for _ in range(len(runs))]
+        tot_l = np.array([r[2] for r in runs_l])
+        runs_d = [one_do(check=False) for _ in range(len(runs))]
+        tot_d = np.array([r[2] for r in runs_d])
     tot = np.array([r[3] for r in runs])
     exp_ms = np.mean([r[1] for r in runs], axis=0)
     mrg_ms = np.mean([r[2] for r in runs], axis=0)
@@ -891,6 +911,7 @@ def run_share29(args):
     # offsets per frontier vertex (counted on the device), over its launches
     exp_bytes = 4.0 * st.dense_edges + 16.0 * st.dense_frontier
     exp_gbs = exp_bytes / (float(np.sum(exp_ms)) * 1e-3) / 1e9
+    share_traffic = measured_share_traffic()
     out = {
         "metric": "GTEPS over the share's scanned edges (one node of 16, staged butterfly messages)",
         "value": round(metrics.gteps(e_share, float(np.median(tot)) * 1e-3), 3), "unit": "GTEPS",
@@ -905,16 +926,27 @@ def run_share29(args):
         "per_level_ms": {"expand": [round(x, 3) for x in exp_ms], "merge": [round(x, 3) for x in mrg_ms]},
         "roofline": {"bound": "hbm", "kernel": "k_merge", "achieved": round(mrg_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(mrg_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": int(merge_bytes),
+                     "traffic": share_traffic["k_merge"]["hbm_bytes_per_launch"] if share_traffic else None,
+                     "bytes_per_launch": int(merge_bytes),
                      "launches": len(runs) * len(mrg_ms)},
         "roofline_expansion": {"bound": "hbm", "kernel": "k_expand", "achieved": round(exp_gbs, 1),
                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": round(exp_gbs / HBM_PEAK_GBS, 4),
                                "bytes_per_traversal": int(exp_bytes),
                                "launches_per_traversal": len(exp_ms),
-                               "ms_per_traversal": round(float(np.sum(exp_ms)), 3)},
+                               "ms_per_traversal": round(float(np.sum(exp_ms)), 3),
+                               "traffic_per_traversal": (share_traffic["k_expand"]["hbm_bytes_per_traversal"]
+                                                         if share_traffic else None)},
+        **({"traffic_source": "profiles/traffic_share29.json"} if share_traffic else {}),
         "exact": bool(exact),
-        "list_messages": {
+        "cpu_baseline": {"value": round(metrics.gteps(m_all, t_oracle), 4), "unit": "GTEPS",
+                         "cores": 1, "kind": "oracle",
+                         "sample": f"the oracle's full traversal of the whole scale-{scale} graph "
+                                   f"from the same source ({t_oracle:.0f} s)"},
+        "edges_scanned_share": int(e_share),
+    }
+    if forms_all:
+        out["list_messages"] = {
             "note": "same traversal with every staged message of fewer than n/32 vertices sent as "
                     "a vertex list (bfs_merge_lists) and the node's own global queue exported as a "
                     "list when it is the smaller message (bfs_frontier_list); merge time includes "
@@ -925,8 +957,8 @@ def run_share29(args):
             "received_bytes_per_level": {"bitmaps": bm_bytes, "lists_where_smaller": mixed_bytes},
             "per_level_ms": {"expand": [round(x, 3) for x in np.mean([r[0] for r in runs_l], axis=0)],
                              "merge": [round(x, 3) for x in np.mean([r[1] for r in runs_l], axis=0)]},
-            "exact": bool(exact_lists)},
-        "direction_optimizing": {
+            "exact": bool(exact_lists)}
+        out["direction_optimizing"] = {
             "note": "same share and source; levels whose frontier holds at least n/24 vertices run "
                     "Phase 1 bottom-up (bfs_expand_bottom_up) with the matching staged messages "
                     "(each node's owned vertices of the next level); GTEPS over the same share "
@@ -937,15 +969,10 @@ def run_share29(args):
             "adjacency_entries_examined_bottom_up": int(runs_d[0][4].bottom_up_edges),
             "per_level_ms": {"expand": [round(x, 3) for x in np.mean([r[0] for r in runs_d], axis=0)],
                              "merge": [round(x, 3) for x in np.mean([r[1] for r in runs_d], axis=0)]},
-            "exact": bool(exact_do)},
-        "cpu_baseline": {"value": round(metrics.gteps(m_all, t_oracle), 4), "unit": "GTEPS",
-                         "cores": 1, "kind": "oracle",
-                         "sample": f"the oracle's full traversal of the whole scale-{scale} graph "
-                                   f"from the same source ({t_oracle:.0f} s)"},
-        "edges_scanned_share": int(e_share),
-    }
+            "exact": bool(exact_do)}
     plan.close()
-    plan_do.close()
+    if plan_do is not None:
+        plan_do.close()
     copy_gbs = measured_copy_gbs()
     for key in ("roofline", "roofline_expansion"):
         out[key]["measured_copy_gbs"] = copy_gbs
@@ -1111,6 +1138,56 @@ def summarize_trace(args):
     print("\n".join(md))
 
 
+def summarize_share_pmc(args):
+    """Writes profiles/traffic_share29.json from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE) of `bench.py --workload share29
+    --share-forms topdown`: the mean HBM bytes per launch of k_merge and per
+    traversal of k_expand over the timed traversals (the last `steps` x
+    `levels` dispatches of each), scaled by the copy-probe factors recorded in
+    profiles/traffic_rmat24.json."""
+    import csv
+    from collections import defaultdict
+
+    fd, wd, run_log = args.summarize_share_pmc
+    line = _bench_line(run_log)
+    steps, levels = int(line["steps"]), int(line["config"]["levels"])
+    with open(os.path.join(ROOT, "profiles", "traffic_rmat24.json")) as f:
+        probe = json.load(f)["copy_probe"]
+
+    def per_dispatch(d, counter):
+        vals = defaultdict(lambda: defaultdict(float))
+        with open(os.path.join(d, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    vals[_short(r["Kernel_Name"])][int(r["Dispatch_Id"])] += float(r["Counter_Value"])
+        return {k: [v[i] for i in sorted(v)][-steps * levels:] for k, v in vals.items()}
+
+    fetch = per_dispatch(fd, "FETCH_SIZE")
+    write = per_dispatch(wd, "WRITE_SIZE")
+    out = {"workload": line["config"]["workload"], "steps": steps, "levels": levels,
+           "commands": [f"rocprofv3 --pmc FETCH_SIZE -d {fd} -o run --output-format csv -- python -u bench.py "
+                        "--workload share29 --share-forms topdown --steps 1",
+                        f"rocprofv3 --pmc WRITE_SIZE -d {wd} -o run --output-format csv -- python -u bench.py "
+                        "--workload share29 --share-forms topdown --steps 1"],
+           "kernel_source_hash": kernel_source_hash(),
+           "copy_probe": probe, "kernels": {}}
+    for k in ("k_expand", "k_merge"):
+        fb = [x * probe["fetch_scale"] * 1024 for x in fetch.get(k, [])]
+        wb = [x * probe["write_scale"] * 1024 for x in write.get(k, [])]
+        if not fb or len(fb) != len(wb):
+            continue
+        rec = {"dispatches": len(fb), "fetch_bytes_per_launch": int(sum(fb) / len(fb)),
+               "write_bytes_per_launch": int(sum(wb) / len(wb)),
+               "hbm_bytes_per_launch": int((sum(fb) + sum(wb)) / len(fb)),
+               "hbm_bytes_per_traversal": int((sum(fb) + sum(wb)) / steps),
+               "per_level_mb": [round((a + b) / 1e6, 1) for a, b in zip(fb[-levels:], wb[-levels:])]}
+        out["kernels"][k] = rec
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "traffic_share29.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def summarize_counters(args):
     """Writes a markdown table of rocprofv3 --pmc counters of a bench.py run:
     for the dominant kernel series the mean per launch over the timed
@@ -1223,6 +1300,10 @@ def main():
     ap.add_argument("--serve-oracle", type=int, default=16,
                     help="sampled served answers also checked against the CPU oracle")
     ap.add_argument("--share-scale", type=int, default=29)
+    ap.add_argument("--share-forms", choices=["all", "topdown"], default="all",
+                    help="share workload: also the list-message and direction-optimizing forms, "
+                         "or the top-down traversals alone (for counter runs)")
+    ap.add_argument("--summarize-share-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "RUN_LOG"))
     ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
                                                          "COPY_WRITE_DIR", "FETCH_RUN_LOG"))
     ap.add_argument("--summarize-trace", nargs=4, metavar=("TRACE_DIR", "RUN_LOG", "OUT_NAME",
@@ -1250,6 +1331,9 @@ def main():
         return
     if args.summarize_counters:
         summarize_counters(args)
+        return
+    if args.summarize_share_pmc:
+        summarize_share_pmc(args)
         return
     if args.workload == "rmat24":
         out = run_single(args, "rmat24", 24, 16)
