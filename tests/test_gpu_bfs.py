@@ -871,6 +871,34 @@ def test_full_size_rmat24_ef16(gpu, rmat24, plan_opts):
     plan.close()
 
 
+@pytest.mark.parametrize("grid", [1, 7, 300, 2048])
+def test_persistent_grid_sizes(gpu, grid):
+    """The cooperative loop's grid barrier (block 0 collects every block's
+    announcement) at one block, at grids that are not multiples of a
+    wavefront or of the 256 threads that poll, and at its 2048-block limit:
+    R-MAT 14 and a grid graph of ~350 levels (two barriers per level)."""
+    import torch
+    for g, srcs in ((gg.rmat(14, 8, seed=0x5EED0014, perm_seed=0xBEEF0014), (0, 777)),
+                    (gg.grid(200, 150, 0.02, seed=17), (5, 12345))):
+        dg = pkg.DeviceGraph.from_csr(g, gpu)
+        plan = pkg.Plan([dg], loop_mode=pkg.LOOP_PERSISTENT, grid_blocks=grid, autotune=-1)
+        for s in srcs:
+            if s >= g.n:
+                continue
+            print(f"[gpu] persistent grid={grid} n={g.n} src={s}", flush=True)
+            try:
+                d, _, st = plan.run(0, int(s))
+            except pkg.BfsError as err:
+                # more blocks than can be co-resident with this kernel's resources
+                assert grid == 2048 and "cooperative launch of at most" in str(err)
+                break
+            torch.cuda.synchronize()
+            ref = oracle.bfs(g, int(s))
+            assert np.array_equal(d.cpu().numpy(), ref)
+            assert st.levels == int(ref.max()) + 1
+        plan.close()
+
+
 def test_graph_replays_match_eager(gpu):
     """The captured level graph is replayed many times per traversal and across
     traversals, with eager launches and synchronisations in between; every
