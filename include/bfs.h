@@ -131,7 +131,7 @@ typedef struct {
                               exchange callback may run large levels bottom-up (see below),
                               and step-wise traversals may call bfs_expand_bottom_up.
                               Distances are the same either way */
-  int32_t mark_mode;       /* bfs_run on a whole graph without queue-only or bottom-up levels:
+  int32_t mark_mode;       /* bfs_run on a whole graph without bottom-up levels:
                               0 or 1 = byte marks: the expansion leaves the bitmaps alone,
                               keeps the hubs it finds in its LDS copy of their visited bits
                               (ORed into a small hub bitmap once per workgroup) and sets one

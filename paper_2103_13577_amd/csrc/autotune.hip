@@ -225,8 +225,8 @@ bfs_status tune_graph(Plan *p, size_t gi) {
         if ((s = trial(c))) return s;
       }
     t = best;
-    // all-dense levels: byte marks against atomic ORs into the bitmap
-    if (p->opt.mark_mode == 0 && best.sparse_div == 0) {
+    // dense levels: byte marks against atomic ORs into the bitmap
+    if (p->opt.mark_mode == 0) {
       Tuning c = best;
       c.mark = 0;
       if ((s = trial(c))) return s;

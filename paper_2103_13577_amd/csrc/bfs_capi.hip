@@ -684,17 +684,20 @@ namespace {
 // finds the new vertices. Called after the reset, before the level loop.
 // With byte marks (a whole graph whose tuning selects them) the expansions
 // leave both bitmaps alone and set one byte per discovered vertex instead;
-// the marks must all be zero when the traversal starts.
+// the marks must all be zero when the traversal starts. Queue-only levels mix
+// with either byte marks (they OR into `visited` themselves and set no mark;
+// every dense level's merge clears the marks it read) but not with the OR
+// into `visited`, whose snapshot in `next` only dense merges keep.
 // The expansion form bfs_run uses for a graph (its flags only; no device
-// work): byte marks, an OR into `visited`, or neither (queue-only levels,
-// bottom-up levels or an exchange keep the two-bitmap form).
+// work): byte marks, an OR into `visited`, or neither (bottom-up levels, an
+// exchange, or queue-only levels without byte marks keep the two-bitmap form).
 void dense_form(bfs_plan_t p, int32_t graph) {
   p->cur_mark = p->cur_into_vis = false;
-  if (p->opt.exchange || p->cur_do || p->tune[graph].sparse_div != 0) return;
+  if (p->opt.exchange || p->cur_do) return;
   const bfs_graph &g = p->graphs[graph];
   if (p->tune[graph].mark && p->lay.mark && g.v_begin == 0 && g.v_end == g.n_global)
     p->cur_mark = true;
-  else
+  else if (p->tune[graph].sparse_div == 0)
     p->cur_into_vis = true;
 }
 

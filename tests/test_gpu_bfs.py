@@ -75,6 +75,11 @@ MODES = [dict(loop_mode=pkg.LOOP_PERSISTENT), dict(loop_mode=pkg.LOOP_HOST),
          # the same all-dense loops with the atomic-OR expansion instead of byte marks
          dict(loop_mode=pkg.LOOP_HOST, sparse_div=-1, hot_words=16384, small_bin=3, wave_bin=6,
               chunk_edges=128, mark_mode=-1),
+         # byte marks on dense levels with queue-only levels between them
+         # (host-driven and captured loops, wide hub copy)
+         dict(loop_mode=pkg.LOOP_HOST, sparse_div=16, hot_words=16384, small_bin=3, wave_bin=6,
+              chunk_edges=128),
+         dict(loop_mode=pkg.LOOP_GRAPH, sparse_div=16, hot_words=16384),
          # the captured loop's level steps launched directly (queue-only levels
          # and the narrow hub copy; all-dense levels with byte marks and the wide copy)
          dict(loop_mode=pkg.LOOP_ENQUEUE, hot_words=2048),
