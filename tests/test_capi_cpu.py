@@ -53,3 +53,36 @@ def test_stats_wrapper_mirrors_c_struct():
     """The Python Stats record carries every field of bfs_stats."""
     import paper_2103_13577_amd as pkg
     assert [f for f, _ in pkg.bfs_stats._fields_] == list(pkg.Stats.__dataclass_fields__)
+
+
+def _header():
+    src = open(os.path.join(ROOT, "include", "bfs.h")).read()
+    return re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+
+
+def _struct_fields(src, name):
+    body = re.search(r"typedef struct\s*\{([^{}]*)\}\s*" + name + r"\s*;", src).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            out.append(re.findall(r"[A-Za-z_][A-Za-z_0-9]*", decl)[-1])
+    return out
+
+
+@pytest.mark.parametrize("name", ["bfs_options", "bfs_tuning", "bfs_stats", "bfs_graph", "bfs_query",
+                                  "bfs_batch_result", "bfs_batch_counters"])
+def test_binding_structs_follow_the_header(name):
+    """Every ctypes mirror lists the C struct's members in the header's order
+    (a missing or reordered field would shift every field after it)."""
+    fields = _struct_fields(_header(), name)
+    assert [f for f, _ in getattr(pkg, name)._fields_] == fields
+
+
+def test_binding_constants_follow_the_header():
+    src = _header()
+    defs = dict(re.findall(r"#define\s+(BFS_(?:LOOP|DIR)_[A-Z_]+)\s+(\d+)", src))
+    for c, v in defs.items():
+        py = c[len("BFS_"):]
+        assert getattr(pkg, py) == int(v), c
+    assert "BFS_LOOP_ENQUEUE" in defs and "BFS_DIR_OPTIMIZING" in defs
